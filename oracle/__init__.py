@@ -1,0 +1,21 @@
+"""FP64 CPU oracle for partially coherent ptychography (pc-ePIE).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, plainly written reference
+that the GPU library is checked against.  Only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the product path
+(the HIP library and its Python binding) never does, and shares no code,
+tables or constants with it.
+
+Every function cites the passage of the paper (Xu et al., "A high-performance
+reconstruction method for partially coherent ptychography", arXiv 2406.06640)
+it follows.  Where the paper is silent the reading used is stated in the
+docstring; the same readings are listed in the design notes of the repository.
+
+Parity status: every function here is pinned by the CPU tests in
+``tests/test_oracle_*.py`` except the mini-batch generalisation of the ePIE
+update for batch size B > 1, which the paper does not define (it is pinned only
+by its B = 1 reduction to sequential ePIE and by convergence): parity unpinned
+for B > 1 beyond those properties.
+"""
+
+from .pcepie import *  # noqa: F401,F403
