@@ -1,0 +1,167 @@
+/*
+ * ptycho.h -- C ABI of the MI355X (gfx950) pc-ePIE reconstruction library.
+ *
+ * Method: partially coherent ePIE ("pc-ePIE") of Xu et al., "A high-performance
+ * reconstruction method for partially coherent ptychography" (arXiv 2406.06640):
+ * the ePIE loop of Fig. 1 with (box 1) a normalised 2D Gaussian convolution of
+ * the estimated diffracted amplitude, Eq. (6)-(7), and (box 2) the complex
+ * amplitude/phase constraint of Eq. (9)-(11), applied in scheduled windows of
+ * iterations (Sec. 3.1, 4.6, 4.8).  K > 1 probe modes are summed incoherently
+ * (the mixed-state model the method is combined with, Sec. 4.1 and 4.4).
+ *
+ * Conventions shared by every entry point
+ *  - Complex arrays are interleaved float pairs (re, im), row-major, C order.
+ *  - Object O: [obj_h][obj_w][2].  Probe P: [n_modes][n][n][2].
+ *  - Intensities I: [n_pos][n][n] float, recorded counts.  Far field: the
+ *    zero frequency sits at pixel (n/2, n/2).  Near field: detector image.
+ *  - Positions: [n_pos][2] int32, the top-left (row, col) of each object box
+ *    o_n = O[row : row + n, col : col + n] (Fig. 1: box, probe and pattern
+ *    have the same size).
+ *  - Propagator (Eq. 1): the unitary 2D DFT (far field), or the paraxial
+ *    free-space transfer function exp(-i pi (u^2 + v^2) / (n^2 F_px)) with
+ *    signed frequency indices u, v and pixel Fresnel number F_px (near field;
+ *    the paper gives the distance, Sec. 3.1, not the formula).
+ *  - mem_kind selects whether a data pointer is host memory (PTYCHO_MEM_HOST)
+ *    or device memory of the current HIP device (PTYCHO_MEM_DEVICE).
+ *  - Every call returns a ptycho_status; on failure ptycho_last_error()
+ *    describes it.  Nothing throws across this boundary.
+ *  - One context is not thread-safe.  All device work is ordered on the
+ *    stream given to ptycho_init; calls that return data synchronise it.
+ */
+#ifndef PTYCHO_H
+#define PTYCHO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptycho_ctx ptycho_ctx; /* opaque; owns all of its device memory */
+
+typedef enum {
+  PTYCHO_OK = 0,
+  PTYCHO_E_INVALID = -1, /* bad argument value (NaN, out of range, bad order) */
+  PTYCHO_E_SHAPE = -2,   /* unsupported n, box outside the object, size mismatch */
+  PTYCHO_E_OOM = -3,     /* device or pinned host allocation failed */
+  PTYCHO_E_HIP = -4,     /* a HIP runtime call failed */
+  PTYCHO_E_NUMERIC = -5, /* a non-finite value appeared; the context is marked failed */
+  PTYCHO_E_STATE = -6    /* the context is failed or the call is out of order */
+} ptycho_status;
+
+enum { PTYCHO_FAR_FIELD = 0, PTYCHO_NEAR_FIELD = 1 };
+enum { PTYCHO_BLUR_AMPLITUDE = 0 /* Eq. (6) */, PTYCHO_BLUR_INTENSITY = 1 /* Eq. (2) */ };
+enum { PTYCHO_MEM_HOST = 0, PTYCHO_MEM_DEVICE = 1 };
+
+typedef struct ptycho_params {
+  /* Frame side n (probe, box and pattern, Fig. 1): 8, 16, 24, 32, 48, 64, 96,
+   * 128, 192, 256, 384, 512, 768 or 1024.  n_modes K in [1, 16]. */
+  int32_t n, n_modes, n_pos, obj_h, obj_w;
+  int32_t geometry;   /* PTYCHO_FAR_FIELD or PTYCHO_NEAR_FIELD */
+  double fresnel_px;  /* near field: F_px = dx^2 / (lambda z) > 0; ignored in the far field */
+  /* Gaussian of Eq. (7): sigma1 along x (columns), sigma2 along y (rows), >= 0;
+   * kernel_size odd in [1, 31] (the paper uses 11, Sec. 3.1).  0 -> delta. */
+  float sigma1, sigma2;
+  int32_t kernel_size;
+  int32_t blur_domain; /* PTYCHO_BLUR_AMPLITUDE (default) or PTYCHO_BLUR_INTENSITY */
+  float eps;           /* >= 0, added to the blurred amplitude in the modulus ratio */
+  /* Complex constraint, Eq. (9)-(10): alpha1, alpha2 in [0, 1]; C-bar of Eq. (11)
+   * is confined to [cbar_min, cbar_max] (the threshold of Sec. 4.8), 0 < min <= max. */
+  float alpha1, alpha2, cbar_min, cbar_max;
+  /* 1-based inclusive window [cc_start, cc_end] of iterations with the constraint,
+   * repeated every cc_period iterations if cc_period > 0; cc_start < 1 disables. */
+  int32_t cc_start, cc_end, cc_period;
+  float obj_step, probe_step;    /* ePIE step sizes alpha, beta (>= 0; 1 = ePIE) */
+  float gamma_obj, gamma_probe;  /* denominator mix in (0, 1]: (1-g) w + g max w; 1 = ePIE */
+  int32_t probe_update_start;    /* probe updated from this 1-based iteration on */
+  int32_t batch;                 /* positions per update, [1, 256]; 1 = sequential ePIE */
+  int32_t orthogonalize;         /* 1: orthogonalise the K > 1 modes after each iteration */
+  uint64_t seed;                 /* random sequence S_n when no explicit order is given */
+} ptycho_params;
+
+/* Fill *p with defaults: n = 64, K = 1, far field, sigma 1, kernel 11, amplitude
+ * blur, eps 1e-6, alpha1 = 1, alpha2 = 0 (phase object, Sec. 3.1), C-bar in
+ * [0.01, 10], constraint off, steps 1, gammas 1, probe update from iteration 1,
+ * batch 1, orthogonalisation on, seed 0.  n_pos/obj_h/obj_w are set to 0. */
+void ptycho_default_params(ptycho_params* p);
+
+/* Create a reconstruction context on the current HIP device.
+ *  intensities [n_pos][n][n], positions [n_pos][2], probe0 [K][n][n][2],
+ *  object0 [obj_h][obj_w][2]: read once (host or device per mem_kind) and copied
+ *  into context-owned device memory; the caller may free them on return.
+ *  hip_stream: a hipStream_t (NULL = the null stream) that must outlive the ctx.
+ * Errors: PTYCHO_E_INVALID (bad parameter, non-finite input, zero-power probe),
+ * PTYCHO_E_SHAPE (unsupported n, a box outside the object), PTYCHO_E_OOM, PTYCHO_E_HIP.
+ * On error *out is NULL. */
+ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
+                          const int32_t* positions, const float* probe0, const float* object0,
+                          int32_t mem_kind, void* hip_stream, ptycho_ctx** out);
+
+/* Run n_iter >= 0 iterations of Fig. 1.  Iteration t (1-based, continuing from
+ * the context's counter) visits the positions in the order order[it][0..n_pos)
+ * (host int32, each row a permutation of 0..n_pos-1), or, when order is NULL,
+ * in a Fisher-Yates permutation driven by SplitMix64(seed XOR t); see
+ * ptycho_permutation.  Consecutive groups of `batch` positions share one update.
+ * err_out (host, n_iter floats, may be NULL) receives the data error
+ * E_t = sum_n sum_q (sqrt(I_n) - A^G_n)^2 / sum_n sum_q I_n of each iteration.
+ * Synchronises the stream.  PTYCHO_E_NUMERIC if E_t is not finite (the context
+ * is then failed); PTYCHO_E_INVALID for a bad order. */
+ptycho_status ptycho_iterate(ptycho_ctx* ctx, int32_t n_iter, const int32_t* order, float* err_out);
+
+/* Copy the current object [obj_h][obj_w][2] / probe [K][n][n][2] into `out`
+ * (host or device per mem_kind).  Synchronises the stream. */
+ptycho_status ptycho_get_object(ptycho_ctx* ctx, float* out, int32_t mem_kind);
+ptycho_status ptycho_get_probe(ptycho_ctx* ctx, float* out, int32_t mem_kind);
+
+/* Replace the object and/or probe (NULL leaves it) and set the completed-iteration
+ * counter to iter >= 0 (resume from a checkpoint).  Clears a failed state. */
+ptycho_status ptycho_set_state(ptycho_ctx* ctx, const float* object, const float* probe,
+                               int32_t iter, int32_t mem_kind);
+
+/* Completed-iteration counter of the context (-1 for NULL). */
+int32_t ptycho_iteration(const ptycho_ctx* ctx);
+
+/* Run ONE batch update (the body of Fig. 1 over the B positions idx[0..B), B in
+ * [1, batch]) as iteration t (decides the probe-update start and the constraint
+ * window) and capture its intermediates for parity checks.  The object and probe
+ * are updated exactly as inside ptycho_iterate; the counter is not changed.
+ * Any output may be NULL.  Outputs (host or device per mem_kind):
+ *   psi      [B][K][n][n][2]  exit waves o_b P_k
+ *   psi_new  [B][K][n][n][2]  back-propagated constrained waves psi'
+ *   factor   [B][n][n]        modulus factor (detector pixel order)
+ *   n_obj    [obj_h][obj_w][2], w_obj [obj_h][obj_w]  object numerator and weight
+ *   n_probe  [K][n][n][2],     v_probe [n][n]          probe numerator and weight
+ *             (probe outputs are zero when t < probe_update_start). */
+ptycho_status ptycho_debug_step(ptycho_ctx* ctx, const int32_t* idx, int32_t B, int32_t t,
+                                float* psi, float* psi_new, float* factor, float* n_obj,
+                                float* w_obj, float* n_probe, float* v_probe, int32_t mem_kind);
+
+/* Per-kernel timing with HIP events recorded on the context stream around each
+ * launch of the kernel classes selected by `mask` (bit i = class i, see
+ * ptycho_kernel_name); 0 disables.  Totals accumulate until reset. */
+ptycho_status ptycho_set_timing(ptycho_ctx* ctx, uint32_t mask);
+/* Accumulated milliseconds and launch count of kernel class `cls`; reset != 0 zeroes it. */
+ptycho_status ptycho_kernel_time(ptycho_ctx* ctx, int32_t cls, double* total_ms, int64_t* launches,
+                                 int32_t reset);
+/* Name of kernel class `cls` (NULL if out of range) and the number of classes. */
+const char* ptycho_kernel_name(int32_t cls);
+int32_t ptycho_kernel_class_count(void);
+
+/* Release all device memory of the context (NULL is a no-op). */
+void ptycho_destroy(ptycho_ctx* ctx);
+
+/* Text of the last error on this context, or of this thread's last failed
+ * ptycho_init / NULL-context call when ctx is NULL.  Never NULL. */
+const char* ptycho_last_error(const ptycho_ctx* ctx);
+
+/* Host-only: the order used for iteration t when none is given -- Fisher-Yates
+ * over 0..n_pos-1 (for i = n_pos-1 .. 1: j = next % (i + 1), swap) with `next`
+ * the SplitMix64 sequence (Steele, Lea, Flood 2014) seeded with seed XOR t.
+ * This is the "random sequence S_n" of Fig. 1; the paper names no generator. */
+ptycho_status ptycho_permutation(uint64_t seed, int32_t t, int32_t n_pos, int32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTYCHO_H */

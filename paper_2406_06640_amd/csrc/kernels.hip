@@ -1,0 +1,1005 @@
+// HIP kernels (gfx950) of one pc-ePIE batch update and its per-iteration bookkeeping.
+//
+// One batch of B scan positions, each with K incoherent probe modes, moves
+// through these passes (frames live in X[b][k][N][N], complex64):
+//   fwd_rows   psi = o_b P_k (box gather fused), 1D transform along x       (Eq. 1)
+//   fwd_cols   1D transform along y; I_mod = sum_k |Psi_k|^2                (mode sum)
+//   blur       A^G = sqrt(I_mod) (x) g  (or I_mod (x) g), factor, data error  (Eq. 6-7, box 1)
+//   inv_cols   Psi' = factor Psi, inverse 1D transform along y
+//   inv_rows   inverse along x -> psi'; dpsi = psi' - o_b P_k; per-slot object
+//              numerator sum_k conj(P_k) dpsi_k; X <- conj(o_b) dpsi_k
+//   probe_acc  N_P,k = sum_b X[b][k] and V = sum_b |o_b|^2 in slot order
+//   obj_wmax / obj_update   W and N_O gathered per object tile in slot order; O update
+//   probe_update            P_k update; sum_k |P_k|^2 refreshed
+//   cc_sums / cc_apply      complex constraint, Eq. (9)-(11) (box 2)
+// Near-field frames use the separable paraxial transfer function: each 1D
+// pass is forward FFT, multiply by h, inverse FFT.  Every reduction runs in a
+// fixed order (no atomics), so results are bitwise reproducible.
+#include "kernels.hpp"
+
+#include <cmath>
+
+#include "fft_lds.hpp"
+
+namespace pty {
+
+const char* const kKernelNames[KC_COUNT] = {
+    "fwd_rows", "fwd_cols", "blur_factor", "inv_cols", "inv_rows_update", "probe_accum", "obj_wmax",
+    "obj_update", "probe_update", "cc_sums", "cc_apply", "gram", "eig", "mode_remix", "err_reduce"};
+
+constexpr int kThreads = 256;
+
+constexpr int largest_divisor_le(int n, int cap) {
+  int best = 1;
+  for (int d = 1; d <= n && d <= cap; ++d)
+    if (n % d == 0) best = d;
+  return best;
+}
+
+// Lines per block: ~2048 elements for row blocks, ~4096 for column blocks,
+// with the column block's LDS (lines + twiddle and transfer tables) <= 64 KiB.
+template <int N>
+struct Cfg {
+  static constexpr int LD = N + 1;  // LDS line stride (float2), padded against bank conflicts
+  static constexpr int ROWS = largest_divisor_le(N, 2048 / N < 1 ? 1 : 2048 / N);
+  static constexpr int CCAP0 = (65536 / 8 - 2 * N) / LD;
+  static constexpr int CCAP1 = 4096 / N < 8 ? 8 : (4096 / N > 64 ? 64 : 4096 / N);
+  static constexpr int COLS = largest_divisor_le(N, CCAP0 < CCAP1 ? CCAP0 : CCAP1);
+  static_assert(N % ROWS == 0 && N % COLS == 0, "tile must divide N");
+};
+
+__device__ __forceinline__ double block_sum_d(double v, double* sh) {
+  // fixed-order tree over the 256 threads of the block
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ float block_max_f(float v, float* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  float r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Row passes
+// ---------------------------------------------------------------------------
+
+// After fft_lines, apply the near-field transfer function (conjugated for the
+// inverse direction) and the inverse transform, so `a` ends as F^-1 h F of the
+// input line (unnormalised by N).
+template <int N, int NL, bool CONJ>
+__device__ __forceinline__ void near_mid(float2* a, int ld, const float2* tw, const float2* __restrict__ h) {
+  for (int e = threadIdx.x; e < NL * N; e += kThreads) {
+    const int l = e / N, x = e - l * N;
+    const float2 hv = h[x];
+    a[l * ld + x] = CONJ ? cmulc(a[l * ld + x], hv) : cmul(a[l * ld + x], hv);
+  }
+  __syncthreads();
+  fft_lines<N, NL, true>(a, ld, tw);
+}
+
+template <int N, bool NEAR>
+__global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                       int ns) {
+  constexpr int L = Cfg<N>::ROWS, LD = Cfg<N>::LD;
+  constexpr int E = (L * N + kThreads - 1) / kThreads;
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* bufA = sm + 2 * N;
+  const int b = blockIdx.y;
+  if (b >= ns) return;
+  const int y0 = blockIdx.x * L;
+  const int2 rc = d.pos[slots[b]];
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  float2 o[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < L * N) {
+      const int ly = e / N, x = e - ly * N;
+      o[i] = d.obj[(size_t)(rc.x + y0 + ly) * p.w_obj + rc.y + x];
+    }
+  }
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  for (int k = 0; k < p.k; ++k) {
+    const float2* pk = d.probe + (size_t)k * N * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < L * N) {
+        const int ly = e / N, x = e - ly * N;
+        bufA[ly * LD + x] = cmul(o[i], pk[(y0 + ly) * N + x]);
+      }
+    }
+    __syncthreads();
+    float2* a = bufA;
+    fft_lines<N, L, false>(a, LD, tw);
+    if (NEAR) near_mid<N, L, false>(a, LD, tw, hn);
+    float2* out = d.X + ((size_t)(b * p.k + k) * N + y0) * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < L * N) {
+        const int ly = e / N, x = e - ly * N;
+        out[ly * N + x] = cscale(a[ly * LD + x], scale);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, bool NEAR>
+__global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                       int ns, DebugPtrs dbg) {
+  constexpr int L = Cfg<N>::ROWS, LD = Cfg<N>::LD;
+  constexpr int E = (L * N + kThreads - 1) / kThreads;
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* bufA = sm + 2 * N;
+  const int b = blockIdx.y;
+  if (b >= ns) return;
+  const int y0 = blockIdx.x * L;
+  const int2 rc = d.pos[slots[b]];
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  float2 o[E], acc[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    acc[i] = make_float2(0.f, 0.f);
+    if (e < L * N) {
+      const int ly = e / N, x = e - ly * N;
+      o[i] = d.obj[(size_t)(rc.x + y0 + ly) * p.w_obj + rc.y + x];
+    }
+  }
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  for (int k = 0; k < p.k; ++k) {
+    float2* fr = d.X + ((size_t)(b * p.k + k) * N + y0) * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < L * N) {
+        const int ly = e / N, x = e - ly * N;
+        bufA[ly * LD + x] = fr[ly * N + x];
+      }
+    }
+    __syncthreads();
+    float2* a = bufA;
+    if (NEAR) {
+      fft_lines<N, L, false>(a, LD, tw);
+      near_mid<N, L, true>(a, LD, tw, hn);
+    } else {
+      fft_lines<N, L, true>(a, LD, tw);
+    }
+    const float2* pk = d.probe + (size_t)k * N * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < L * N) {
+        const int ly = e / N, x = e - ly * N;
+        const float2 psi_new = cscale(a[ly * LD + x], scale);
+        const float2 pv = pk[(y0 + ly) * N + x];
+        const float2 dpsi = csub(psi_new, cmul(o[i], pv));
+        acc[i] = cadd(acc[i], cmulc(dpsi, pv));  // conj(P) dpsi
+        fr[ly * N + x] = cmulc(dpsi, o[i]);       // conj(o) dpsi
+        if (dbg.psi_new) dbg.psi_new[((size_t)(b * p.k + k) * N + y0 + ly) * N + x] = psi_new;
+      }
+    }
+    __syncthreads();
+  }
+  float2* dO = d.dO + ((size_t)b * N + y0) * N;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < L * N) dO[e] = acc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column passes
+// ---------------------------------------------------------------------------
+
+template <int N, bool NEAR>
+__global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, int ns) {
+  constexpr int C = Cfg<N>::COLS, LD = Cfg<N>::LD;
+  constexpr int E = (C * N + kThreads - 1) / kThreads;
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* bufA = sm + 2 * N;
+  const int b = blockIdx.y;
+  if (b >= ns) return;
+  const int x0 = blockIdx.x * C;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  float acc[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) acc[i] = 0.f;
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  for (int k = 0; k < p.k; ++k) {
+    float2* fr = d.X + (size_t)(b * p.k + k) * N * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < C * N) {
+        const int y = e / C, c = e - y * C;
+        bufA[c * LD + y] = fr[(size_t)y * N + x0 + c];
+      }
+    }
+    __syncthreads();
+    float2* a = bufA;
+    fft_lines<N, C, false>(a, LD, tw);
+    if (NEAR) near_mid<N, C, false>(a, LD, tw, hn);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < C * N) {
+        const int y = e / C, c = e - y * C;
+        const float2 v = cscale(a[c * LD + y], scale);
+        fr[(size_t)y * N + x0 + c] = v;
+        acc[i] += v.x * v.x + v.y * v.y;
+      }
+    }
+    __syncthreads();
+  }
+  float* q = d.q + (size_t)b * N * N;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < C * N) {
+      const int y = e / C, c = e - y * C;
+      q[(size_t)y * N + x0 + c] = acc[i];
+    }
+  }
+}
+
+template <int N, bool NEAR>
+__global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, int ns) {
+  constexpr int C = Cfg<N>::COLS, LD = Cfg<N>::LD;
+  constexpr int E = (C * N + kThreads - 1) / kThreads;
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* bufA = sm + 2 * N;
+  const int b = blockIdx.y;
+  if (b >= ns) return;
+  const int x0 = blockIdx.x * C;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  float f[E];
+  const float* fac = d.fac + (size_t)b * N * N;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    f[i] = 0.f;
+    if (e < C * N) {
+      const int y = e / C, c = e - y * C;
+      f[i] = fac[(size_t)y * N + x0 + c];
+    }
+  }
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  for (int k = 0; k < p.k; ++k) {
+    float2* fr = d.X + (size_t)(b * p.k + k) * N * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < C * N) {
+        const int y = e / C, c = e - y * C;
+        bufA[c * LD + y] = cscale(fr[(size_t)y * N + x0 + c], f[i]);
+      }
+    }
+    __syncthreads();
+    float2* a = bufA;
+    if (NEAR) {
+      fft_lines<N, C, false>(a, LD, tw);
+      near_mid<N, C, true>(a, LD, tw, hn);
+    } else {
+      fft_lines<N, C, true>(a, LD, tw);
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < C * N) {
+        const int y = e / C, c = e - y * C;
+        fr[(size_t)y * N + x0 + c] = cscale(a[c * LD + y], scale);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Box 1: Gaussian blur of the modelled amplitude and the modulus factor
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_blur_factor(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                          int ns, int tb) {
+  constexpr int S = kBlurTile + 2 * kMaxHalf;
+  __shared__ float qs[S][S + 1];
+  __shared__ float hs[S][kBlurTile + 1];
+  __shared__ double red[kThreads];
+  const int b = blockIdx.z;
+  if (b >= ns) return;
+  const int n = p.n, h = p.ks_half;
+  const int ty0 = blockIdx.y * tb, tx0 = blockIdx.x * tb;
+  const int s = tb + 2 * h;
+  const float* q = d.q + (size_t)b * n * n;
+  for (int e = threadIdx.x; e < s * s; e += kThreads) {
+    const int yy = e / s, xx = e - yy * s;
+    int gy = ty0 - h + yy, gx = tx0 - h + xx;
+    gy = ((gy % n) + n) % n;
+    gx = ((gx % n) + n) % n;
+    const float v = q[(size_t)gy * n + gx];
+    qs[yy][xx] = p.blur_intensity ? v : sqrtf(v);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < s * tb; e += kThreads) {
+    const int yy = e / tb, x = e - yy * tb;
+    float acc = p.gx[0] * qs[yy][x + h];
+    for (int dx = 1; dx <= h; ++dx) acc += p.gx[dx] * (qs[yy][x + h - dx] + qs[yy][x + h + dx]);
+    hs[yy][x] = acc;
+  }
+  __syncthreads();
+  const int pat = slots[b];
+  const float* amp = d.amp + (size_t)pat * n * n;
+  float* fac = d.fac + (size_t)b * n * n;
+  double err = 0.0;
+  for (int e = threadIdx.x; e < tb * tb; e += kThreads) {
+    const int y = e / tb, x = e - y * tb;
+    float g = p.gy[0] * hs[y + h][x];
+    for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (hs[y + h - dy][x] + hs[y + h + dy][x]);
+    const size_t idx = (size_t)(ty0 + y) * n + tx0 + x;
+    const float a = amp[idx];
+    float ag, f;
+    if (p.blur_intensity) {
+      ag = sqrtf(g);
+      f = a / sqrtf(g + p.eps * p.eps);
+    } else {
+      ag = g;
+      f = a / (g + p.eps);
+    }
+    fac[idx] = f;
+    const double dd = (double)a - (double)ag;
+    err += dd * dd;
+  }
+  const double tot = block_sum_d(err, red);
+  if (threadIdx.x == 0) {
+    const int tiles_x = n / tb;
+    d.err_part[(size_t)pat * tiles_x * tiles_x + blockIdx.y * tiles_x + blockIdx.x] = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe numerator / weight, object gather and updates
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_probe_accum(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                          int ns) {
+  __shared__ int2 bp[kMaxBatch];
+  __shared__ float red[kThreads];
+  const int n = p.n;
+  for (int b = threadIdx.x; b < ns; b += kThreads) bp[b] = d.pos[slots[b]];
+  __syncthreads();
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  float vmax = 0.f;
+  if (pix < n * n) {
+    const int y = pix / n, x = pix - y * n;
+    const size_t nn = (size_t)n * n;
+    for (int k = 0; k < p.k; ++k) {
+      float2 s = make_float2(0.f, 0.f);
+      for (int b = 0; b < ns; ++b) s = cadd(s, d.X[(size_t)(b * p.k + k) * nn + pix]);
+      d.nP[(size_t)k * nn + pix] = s;
+    }
+    float v = 0.f;
+    for (int b = 0; b < ns; ++b) {
+      const float2 o = d.obj[(size_t)(bp[b].x + y) * p.w_obj + bp[b].y + x];
+      v += o.x * o.x + o.y * o.y;
+    }
+    d.V[pix] = v;
+    vmax = v;
+  }
+  const float m = block_max_f(vmax, red);
+  if (threadIdx.x == 0) d.maxv_part[blockIdx.x] = m;
+}
+
+// Mark the slots whose boxes intersect this object tile; returns whether any does.
+__device__ __forceinline__ bool tile_hits(const DevBufs& d, const int* slots, int ns, int n, int r0, int c0,
+                                          int r1, int c1, int2* bp, int* hit, int* any) {
+  if (threadIdx.x == 0) *any = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < ns; b += kThreads) {
+    const int2 rc = d.pos[slots[b]];
+    bp[b] = rc;
+    const int h = (rc.x < r1 && rc.x + n > r0 && rc.y < c1 && rc.y + n > c0) ? 1 : 0;
+    hit[b] = h;
+    if (h) *any = 1;  // benign: every writer stores 1
+  }
+  __syncthreads();
+  return *any != 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_obj_wmax(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                       int ns) {
+  __shared__ int2 bp[kMaxBatch];
+  __shared__ int hit[kMaxBatch];
+  __shared__ int any;
+  __shared__ float red[kThreads];
+  const int n = p.n;
+  const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  const bool touched = tile_hits(d, slots, ns, n, r0, c0, r0 + kObjTile, c0 + kObjTile, bp, hit, &any);
+  if (!touched) {
+    if (threadIdx.x == 0) d.maxw_part[tile] = 0.f;
+    return;
+  }
+  float m = 0.f;
+  for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
+    const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
+    if (r >= p.h_obj || c >= p.w_obj) continue;
+    float w = 0.f;
+    for (int b = 0; b < ns; ++b) {
+      if (!hit[b]) continue;
+      const int yy = r - bp[b].x, xx = c - bp[b].y;
+      if (yy >= 0 && yy < n && xx >= 0 && xx < n) w += d.pw[yy * n + xx];
+    }
+    m = fmaxf(m, w);
+  }
+  m = block_max_f(m, red);
+  if (threadIdx.x == 0) d.maxw_part[tile] = m;
+}
+
+__device__ __forceinline__ float reduce_max_parts(const float* parts, int count, float* red) {
+  float m = 0.f;
+  for (int i = threadIdx.x; i < count; i += kThreads) m = fmaxf(m, parts[i]);
+  return block_max_f(m, red);
+}
+
+__global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                         int ns, DebugPtrs dbg) {
+  __shared__ int2 bp[kMaxBatch];
+  __shared__ int hit[kMaxBatch];
+  __shared__ int any;
+  __shared__ float red[kThreads];
+  const int n = p.n;
+  const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
+  const bool touched = tile_hits(d, slots, ns, n, r0, c0, r0 + kObjTile, c0 + kObjTile, bp, hit, &any);
+  if (!touched) return;
+  const float maxw = reduce_max_parts(d.maxw_part, gridDim.x * gridDim.y, red);
+  const size_t nn = (size_t)n * n;
+  for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
+    const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
+    if (r >= p.h_obj || c >= p.w_obj) continue;
+    float w = 0.f;
+    float2 num = make_float2(0.f, 0.f);
+    bool cov = false;
+    for (int b = 0; b < ns; ++b) {
+      if (!hit[b]) continue;
+      const int yy = r - bp[b].x, xx = c - bp[b].y;
+      if (yy >= 0 && yy < n && xx >= 0 && xx < n) {
+        w += d.pw[yy * n + xx];
+        num = cadd(num, d.dO[(size_t)b * nn + yy * n + xx]);
+        cov = true;
+      }
+    }
+    if (!cov) continue;
+    const size_t oi = (size_t)r * p.w_obj + c;
+    if (dbg.n_obj) {
+      dbg.n_obj[oi] = num;
+      dbg.w_obj[oi] = w;
+    }
+    const float den = (1.0f - p.gamma_obj) * w + p.gamma_obj * maxw;
+    if (den > 0.f) {
+      const float s = p.obj_step / den;
+      float2 o = d.obj[oi];
+      o.x += s * num.x;
+      o.y += s * num.y;
+      d.obj[oi] = o;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_probe_update(DevParams p, DevBufs d, int nparts) {
+  __shared__ float red[kThreads];
+  const float maxv = reduce_max_parts(d.maxv_part, nparts, red);
+  const int n = p.n;
+  const size_t nn = (size_t)n * n;
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  if (pix >= n * n) return;
+  const float den = (1.0f - p.gamma_probe) * d.V[pix] + p.gamma_probe * maxv;
+  float pw = 0.f;
+  for (int k = 0; k < p.k; ++k) {
+    float2 v = d.probe[(size_t)k * nn + pix];
+    if (den > 0.f) {
+      const float s = p.probe_step / den;
+      const float2 np = d.nP[(size_t)k * nn + pix];
+      v.x += s * np.x;
+      v.y += s * np.y;
+      d.probe[(size_t)k * nn + pix] = v;
+    }
+    pw += v.x * v.x + v.y * v.y;
+  }
+  d.pw[pix] = pw;
+}
+
+__global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
+  const int n = p.n;
+  const size_t nn = (size_t)n * n;
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  if (pix >= n * n) return;
+  float pw = 0.f;
+  for (int k = 0; k < p.k; ++k) {
+    const float2 v = d.probe[(size_t)k * nn + pix];
+    pw += v.x * v.x + v.y * v.y;
+  }
+  d.pw[pix] = pw;
+}
+
+// ---------------------------------------------------------------------------
+// Box 2: complex constraint, Eq. (9)-(11)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_cc_sums(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                      int ns) {
+  __shared__ double red[kThreads];
+  const int b = blockIdx.y;
+  if (b >= ns) return;
+  const int n = p.n;
+  const int2 rc = d.pos[slots[b]];
+  const int base = blockIdx.x * kCcChunk;
+  float sa = 0.f, sp = 0.f;
+  for (int e = base + threadIdx.x; e < base + kCcChunk && e < n * n; e += kThreads) {
+    const int y = e / n, x = e - y * n;
+    const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
+    const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
+    sa += fabsf(logf(a));
+    sp += fabsf(atan2f(o.y, o.x));
+  }
+  const double ta = block_sum_d((double)sa, red);
+  const double tp = block_sum_d((double)sp, red);
+  if (threadIdx.x == 0) d.cc_part[(size_t)b * gridDim.x + blockIdx.x] = make_double2(ta, tp);
+}
+
+__global__ __launch_bounds__(kThreads) void k_cc_apply(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                       int ns, int nchunks) {
+  __shared__ int2 bp[kMaxBatch];
+  __shared__ int hit[kMaxBatch];
+  __shared__ int any;
+  __shared__ double red[kThreads];
+  const int n = p.n;
+  const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
+  const bool touched = tile_hits(d, slots, ns, n, r0, c0, r0 + kObjTile, c0 + kObjTile, bp, hit, &any);
+  if (!touched) return;
+  double sa = 0.0, sp = 0.0;
+  const int cnt = ns * nchunks;
+  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+    sa += d.cc_part[i].x;
+    sp += d.cc_part[i].y;
+  }
+  sa = block_sum_d(sa, red);
+  sp = block_sum_d(sp, red);
+  if (!(sp > 0.0)) return;
+  float cbar = (float)(sa / sp);
+  cbar = fminf(fmaxf(cbar, p.cbar_min), p.cbar_max);
+  const float inv_c = 1.0f / cbar;
+  for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
+    const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
+    if (r >= p.h_obj || c >= p.w_obj) continue;
+    bool cov = false;
+    for (int b = 0; b < ns && !cov; ++b) {
+      if (!hit[b]) continue;
+      const int yy = r - bp[b].x, xx = c - bp[b].y;
+      cov = (yy >= 0 && yy < n && xx >= 0 && xx < n);
+    }
+    if (!cov) continue;
+    const size_t oi = (size_t)r * p.w_obj + c;
+    const float2 o = d.obj[oi];
+    const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
+    const float phi = atan2f(o.y, o.x);
+    const float ac = expf((1.0f - p.alpha1) * lna + p.alpha1 * cbar * phi);
+    const float pc = (1.0f - p.alpha2) * phi + p.alpha2 * inv_c * lna;
+    float sn, cs;
+    sincosf(pc, &sn, &cs);
+    d.obj[oi] = make_float2(ac * cs, ac * sn);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mode orthogonalisation (K > 1) and the data error
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_gram(DevParams p, DevBufs d) {
+  __shared__ double red[kThreads];
+  // blockIdx.y = pair index (i <= j), blockIdx.x = pixel chunk
+  int pair = blockIdx.y, i = 0;
+  while (pair >= p.k - i) {
+    pair -= p.k - i;
+    ++i;
+  }
+  const int j = i + pair;
+  const int nn = p.n * p.n;
+  const int chunk = (nn + kGramBlocks - 1) / kGramBlocks;
+  const int lo = blockIdx.x * chunk, hi = min(nn, lo + chunk);
+  const float2* pi = d.probe + (size_t)i * nn;
+  const float2* pj = d.probe + (size_t)j * nn;
+  double re = 0.0, im = 0.0;
+  for (int e = lo + threadIdx.x; e < hi; e += kThreads) {
+    const float2 a = pi[e], bq = pj[e];
+    // conj(P_i) P_j
+    re += (double)a.x * bq.x + (double)a.y * bq.y;
+    im += (double)a.x * bq.y - (double)a.y * bq.x;
+  }
+  re = block_sum_d(re, red);
+  im = block_sum_d(im, red);
+  if (threadIdx.x == 0) d.gram_part[(size_t)blockIdx.y * kGramBlocks + blockIdx.x] = make_double2(re, im);
+}
+
+// Hermitian eigendecomposition by cyclic complex Jacobi rotations (double),
+// one thread; K <= 16.
+__global__ void k_eig(DevParams p, DevBufs d) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int K = p.k;
+  double ar[kMaxModes][kMaxModes], ai[kMaxModes][kMaxModes];
+  double vr[kMaxModes][kMaxModes], vi[kMaxModes][kMaxModes];
+  int pair = 0;
+  for (int i = 0; i < K; ++i)
+    for (int j = i; j < K; ++j, ++pair) {
+      double sr = 0.0, si = 0.0;
+      for (int c = 0; c < kGramBlocks; ++c) {
+        sr += d.gram_part[(size_t)pair * kGramBlocks + c].x;
+        si += d.gram_part[(size_t)pair * kGramBlocks + c].y;
+      }
+      ar[i][j] = sr;
+      ai[i][j] = si;
+      ar[j][i] = sr;
+      ai[j][i] = -si;
+    }
+  for (int i = 0; i < K; ++i) {
+    ai[i][i] = 0.0;
+    for (int j = 0; j < K; ++j) {
+      vr[i][j] = (i == j) ? 1.0 : 0.0;
+      vi[i][j] = 0.0;
+    }
+  }
+  double scale = 0.0;
+  for (int i = 0; i < K; ++i) scale += fabs(ar[i][i]);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < K; ++i)
+      for (int j = i + 1; j < K; ++j) off += ar[i][j] * ar[i][j] + ai[i][j] * ai[i][j];
+    if (off <= 1e-30 * scale * scale) break;
+    for (int pp = 0; pp < K; ++pp)
+      for (int qq = pp + 1; qq < K; ++qq) {
+        const double gr = ar[pp][qq], gi = ai[pp][qq];
+        const double mag = sqrt(gr * gr + gi * gi);
+        if (mag == 0.0) continue;
+        // A_pq = mag e^{i th}; rotate with a real Jacobi angle on the phase-removed pair
+        const double er = gr / mag, ei = gi / mag;  // e^{i th}
+        const double app = ar[pp][pp], aqq = ar[qq][qq];
+        const double tau = (aqq - app) / (2.0 * mag);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        // unitary J: columns p,q of the identity replaced by
+        //   J_pp = c, J_pq = s e^{i th}, J_qp = -s e^{-i th}, J_qq = c ; A <- J^H A J
+        for (int m = 0; m < K; ++m) {  // A <- A J (columns p, q)
+          const double xr = ar[m][pp], xi = ai[m][pp], yr = ar[m][qq], yi = ai[m][qq];
+          // new col p = c x - s e^{-i th} y ; new col q = s e^{i th} x + c y
+          ar[m][pp] = c * xr - s * (er * yr + ei * yi);
+          ai[m][pp] = c * xi - s * (er * yi - ei * yr);
+          ar[m][qq] = s * (er * xr - ei * xi) + c * yr;
+          ai[m][qq] = s * (er * xi + ei * xr) + c * yi;
+          const double ur = vr[m][pp], ui = vi[m][pp], wr = vr[m][qq], wi = vi[m][qq];
+          vr[m][pp] = c * ur - s * (er * wr + ei * wi);
+          vi[m][pp] = c * ui - s * (er * wi - ei * wr);
+          vr[m][qq] = s * (er * ur - ei * ui) + c * wr;
+          vi[m][qq] = s * (er * ui + ei * ur) + c * wi;
+        }
+        for (int m = 0; m < K; ++m) {  // A <- J^H A (rows p, q)
+          const double xr = ar[pp][m], xi = ai[pp][m], yr = ar[qq][m], yi = ai[qq][m];
+          // new row p = c x - s e^{i th} y ; new row q = s e^{-i th} x + c y
+          ar[pp][m] = c * xr - s * (er * yr - ei * yi);
+          ai[pp][m] = c * xi - s * (er * yi + ei * yr);
+          ar[qq][m] = s * (er * xr + ei * xi) + c * yr;
+          ai[qq][m] = s * (er * xi - ei * xr) + c * yi;
+        }
+        ar[pp][qq] = ai[pp][qq] = ar[qq][pp] = ai[qq][pp] = 0.0;
+        ai[pp][pp] = ai[qq][qq] = 0.0;
+      }
+  }
+  // sort by eigenvalue, descending (stable selection)
+  int ord[kMaxModes];
+  bool used[kMaxModes];
+  for (int i = 0; i < K; ++i) used[i] = false;
+  for (int r = 0; r < K; ++r) {
+    int best = -1;
+    for (int i = 0; i < K; ++i)
+      if (!used[i] && (best < 0 || ar[i][i] > ar[best][best])) best = i;
+    used[best] = true;
+    ord[r] = best;
+  }
+  for (int r = 0; r < K; ++r) {
+    const int col = ord[r];
+    // phase: largest-magnitude entry (first on ties) made real positive
+    int im = 0;
+    double mbest = -1.0;
+    for (int i = 0; i < K; ++i) {
+      const double m2 = vr[i][col] * vr[i][col] + vi[i][col] * vi[i][col];
+      if (m2 > mbest) {
+        mbest = m2;
+        im = i;
+      }
+    }
+    const double mg = sqrt(mbest);
+    const double pr = vr[im][col] / mg, pi = -vi[im][col] / mg;  // conj(phase)
+    for (int i = 0; i < K; ++i) {
+      const double xr = vr[i][col], xi = vi[i][col];
+      d.vmix[i * K + r] = make_float2((float)(xr * pr - xi * pi), (float)(xr * pi + xi * pr));
+    }
+    d.eig[r] = ar[col][col];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_remix(DevParams p, DevBufs d) {
+  const int n = p.n;
+  const size_t nn = (size_t)n * n;
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  if (pix >= n * n) return;
+  float2 in[kMaxModes];
+  for (int i = 0; i < p.k; ++i) in[i] = d.probe[(size_t)i * nn + pix];
+  float pw = 0.f;
+  for (int j = 0; j < p.k; ++j) {
+    float2 s = make_float2(0.f, 0.f);
+    for (int i = 0; i < p.k; ++i) s = cadd(s, cmul(in[i], d.vmix[i * p.k + j]));
+    d.probe[(size_t)j * nn + pix] = s;
+    pw += s.x * s.x + s.y * s.y;
+  }
+  d.pw[pix] = pw;
+}
+
+__global__ __launch_bounds__(kThreads) void k_err_reduce(const double* __restrict__ part, int count,
+                                                         double inv_denom, float* out) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += kThreads) s += part[i];
+  s = block_sum_d(s, red);
+  if (threadIdx.x == 0) *out = (float)(s * inv_denom);
+}
+
+// ---------------------------------------------------------------------------
+// Init-time and debug helpers
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_prepare_amp(const float* __restrict__ inten, float* amp, int n,
+                                                          int shift, int* bad, double* sum_part) {
+  __shared__ double red[kThreads];
+  const int pat = blockIdx.y;
+  const size_t nn = (size_t)n * n;
+  double s = 0.0;
+  int nbad = 0;
+  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n * n; e += kThreads * gridDim.x) {
+    const int y = e / n, x = e - y * n;
+    float v = inten[pat * nn + e];
+    if (!isfinite(v)) {
+      ++nbad;
+      v = 0.f;
+    }
+    v = fmaxf(v, 0.f);
+    // far field: move the zero frequency from (n/2, n/2) to (0, 0)
+    const int yo = shift ? (y + n / 2) % n : y;
+    const int xo = shift ? (x + n / 2) % n : x;
+    amp[pat * nn + (size_t)yo * n + xo] = sqrtf(v);
+    s += (double)v;
+  }
+  s = block_sum_d(s, red);
+  const double tb = block_sum_d((double)nbad, red);
+  if (threadIdx.x == 0) {
+    sum_part[(size_t)pat * gridDim.x + blockIdx.x] = s;
+    bad[(size_t)pat * gridDim.x + blockIdx.x] = (int)tb;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_exit_waves(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                         int ns, float2* out) {
+  const int n = p.n;
+  const size_t nn = (size_t)n * n;
+  const int b = blockIdx.y;
+  if (b >= ns) return;
+  const int2 rc = d.pos[slots[b]];
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  if (pix >= n * n) return;
+  const int y = pix / n, x = pix - y * n;
+  const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
+  for (int k = 0; k < p.k; ++k) out[((size_t)b * p.k + k) * nn + pix] = cmul(o, d.probe[(size_t)k * nn + pix]);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+bool supported_n(int n) {
+  switch (n) {
+    case 8: case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384:
+    case 512: case 768: case 1024:
+      return true;
+    default:
+      return false;
+  }
+}
+
+#define PTY_DISPATCH_N(n, MACRO) \
+  switch (n) {                   \
+    MACRO(8) MACRO(16) MACRO(24) MACRO(32) MACRO(48) MACRO(64) MACRO(96) MACRO(128) MACRO(192) MACRO(256) \
+    MACRO(384) MACRO(512) MACRO(768) MACRO(1024) default : return hipErrorInvalidValue; \
+  }
+
+template <int N, bool NEAR>
+static hipError_t fwd_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                             hipStream_t s) {
+  constexpr int L = Cfg<N>::ROWS;
+  const size_t sh = sizeof(float2) * (2 * N + L * Cfg<N>::LD);
+  hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(N / L, bmax), dim3(kThreads), sh, s, p, d, slots, ns);
+  return hipGetLastError();
+}
+template <int N, bool NEAR>
+static hipError_t inv_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                             const DebugPtrs& dbg, hipStream_t s) {
+  constexpr int L = Cfg<N>::ROWS;
+  const size_t sh = sizeof(float2) * (2 * N + L * Cfg<N>::LD);
+  hipLaunchKernelGGL((k_inv_rows<N, NEAR>), dim3(N / L, bmax), dim3(kThreads), sh, s, p, d, slots, ns, dbg);
+  return hipGetLastError();
+}
+template <int N, bool NEAR>
+static hipError_t fwd_cols_t(const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s) {
+  constexpr int C = Cfg<N>::COLS;
+  const size_t sh = sizeof(float2) * (2 * N + C * Cfg<N>::LD);
+  hipLaunchKernelGGL((k_fwd_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, ns);
+  return hipGetLastError();
+}
+template <int N, bool NEAR>
+static hipError_t inv_cols_t(const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s) {
+  constexpr int C = Cfg<N>::COLS;
+  const size_t sh = sizeof(float2) * (2 * N + C * Cfg<N>::LD);
+  hipLaunchKernelGGL((k_inv_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
+                           int bmax, hipStream_t s) {
+#define PTY_CASE(N) \
+  case N:           \
+    return near ? fwd_rows_t<N, true>(p, d, slots, ns, bmax, s) : fwd_rows_t<N, false>(p, d, slots, ns, bmax, s);
+  PTY_DISPATCH_N(n, PTY_CASE)
+#undef PTY_CASE
+}
+hipError_t launch_inv_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
+                           int bmax, const DebugPtrs& dbg, hipStream_t s) {
+#define PTY_CASE(N)                                                  \
+  case N:                                                            \
+    return near ? inv_rows_t<N, true>(p, d, slots, ns, bmax, dbg, s) \
+                : inv_rows_t<N, false>(p, d, slots, ns, bmax, dbg, s);
+  PTY_DISPATCH_N(n, PTY_CASE)
+#undef PTY_CASE
+}
+hipError_t launch_fwd_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax,
+                           hipStream_t s) {
+#define PTY_CASE(N) \
+  case N:           \
+    return near ? fwd_cols_t<N, true>(p, d, ns, bmax, s) : fwd_cols_t<N, false>(p, d, ns, bmax, s);
+  PTY_DISPATCH_N(n, PTY_CASE)
+#undef PTY_CASE
+}
+hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax,
+                           hipStream_t s) {
+#define PTY_CASE(N) \
+  case N:           \
+    return near ? inv_cols_t<N, true>(p, d, ns, bmax, s) : inv_cols_t<N, false>(p, d, ns, bmax, s);
+  PTY_DISPATCH_N(n, PTY_CASE)
+#undef PTY_CASE
+}
+
+static int blur_tb(int n) { return (n % 32 == 0) ? 32 : (n % 16 == 0 ? 16 : 8); }
+int n_blur_tiles(int n) {
+  const int t = n / blur_tb(n);
+  return t * t;
+}
+int n_obj_tiles(const DevParams& p) {
+  return ((p.h_obj + kObjTile - 1) / kObjTile) * ((p.w_obj + kObjTile - 1) / kObjTile);
+}
+int n_probe_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
+int n_cc_chunks(int n) { return (n * n + kCcChunk - 1) / kCcChunk; }
+
+hipError_t launch_blur_factor(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                              hipStream_t s) {
+  const int tb = blur_tb(p.n);
+  hipLaunchKernelGGL(k_blur_factor, dim3(p.n / tb, p.n / tb, bmax), dim3(kThreads), 0, s, p, d, slots, ns, tb);
+  return hipGetLastError();
+}
+hipError_t launch_probe_accum(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_accum, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d, slots, ns);
+  return hipGetLastError();
+}
+static dim3 obj_grid(const DevParams& p) {
+  return dim3((p.w_obj + kObjTile - 1) / kObjTile, (p.h_obj + kObjTile - 1) / kObjTile);
+}
+hipError_t launch_obj_wmax(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_wmax, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns);
+  return hipGetLastError();
+}
+hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns,
+                             const DebugPtrs& dbg, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_update, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, dbg);
+  return hipGetLastError();
+}
+hipError_t launch_probe_update(const DevParams& p, const DevBufs& d, hipStream_t s) {
+  const int nb = n_probe_blocks(p.n);
+  hipLaunchKernelGGL(k_probe_update, dim3(nb), dim3(kThreads), 0, s, p, d, nb);
+  return hipGetLastError();
+}
+hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
+  return hipGetLastError();
+}
+hipError_t launch_cc_sums(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_cc_sums, dim3(n_cc_chunks(p.n), bmax), dim3(kThreads), 0, s, p, d, slots, ns);
+  return hipGetLastError();
+}
+hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                           hipStream_t s) {
+  (void)bmax;
+  hipLaunchKernelGGL(k_cc_apply, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, n_cc_chunks(p.n));
+  return hipGetLastError();
+}
+hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s) {
+  const int pairs = p.k * (p.k + 1) / 2;
+  hipLaunchKernelGGL(k_gram, dim3(kGramBlocks, pairs), dim3(kThreads), 0, s, p, d);
+  return hipGetLastError();
+}
+hipError_t launch_eig(const DevParams& p, const DevBufs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig, dim3(1), dim3(64), 0, s, p, d);
+  return hipGetLastError();
+}
+hipError_t launch_remix(const DevParams& p, const DevBufs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_remix, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
+  return hipGetLastError();
+}
+hipError_t launch_err_reduce(const double* part, int count, double inv_denom, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(kThreads), 0, s, part, count, inv_denom, out);
+  return hipGetLastError();
+}
+hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, bool shift, int* bad,
+                              double* sum_part, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare_amp, dim3(8, n_pos), dim3(kThreads), 0, s, inten, amp, n, shift ? 1 : 0, bad,
+                     sum_part);
+  return hipGetLastError();
+}
+hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* slots, int ns, float2* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_exit_waves, dim3(n_probe_blocks(p.n), ns), dim3(kThreads), 0, s, p, d, slots, ns, out);
+  return hipGetLastError();
+}
+
+}  // namespace pty

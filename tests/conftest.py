@@ -17,3 +17,14 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.default_rng(20240606)
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _library_built():
+    """Build libptycho.so in-tree once if it is missing (a fresh checkout)."""
+    import importlib
+    lib = os.path.join(ROOT, "paper_2406_06640_amd", "_lib", "libptycho.so")
+    if not os.path.exists(lib):
+        build = importlib.import_module("paper_2406_06640_amd.build")
+        build.build()
+    yield

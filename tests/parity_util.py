@@ -1,0 +1,96 @@
+"""Shared helpers for the GPU parity tests: build a seeded case, run the same
+batch step or iterations through the C ABI and through the FP64 oracle."""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import datagen
+import oracle as ora
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def make_case(n=32, k=1, geometry=0, obj=(80, 80), n_side=4, step=8, radius=None, seed=11,
+              sigma_data=1.0, fresnel_px=None, wavelengths=(1.0,), jitter=1, n_pos=None, screen=None):
+    spec = dict(datagen.CONFIGS["c1"])
+    radius = radius if radius is not None else max(n // 4, 2)
+    if geometry == 1 and fresnel_px is None:
+        fresnel_px = 20.0 / float(radius * radius)
+    spec.update(geometry=geometry, obj=obj, n=n, n_side=n_side, step=step, jitter=jitter, k=k,
+                powers=tuple(2.0 ** -i for i in range(k)), radius=radius, sigma_data=sigma_data,
+                wavelengths=wavelengths, fresnel_px=fresnel_px or 0.0, screen=screen,
+                defocus=1.0 if geometry == 0 else 0.0)
+    s = datagen.make_scan(spec, seed, n_pos=n_pos)
+    s["spec"] = spec
+    return s
+
+
+# parameter names shared by the oracle's Params and the C struct
+_SHARED = ["n", "n_modes", "geometry", "fresnel_px", "sigma1", "sigma2", "kernel_size", "blur_domain", "eps",
+           "alpha1", "alpha2", "cbar_min", "cbar_max", "cc_start", "cc_end", "cc_period", "obj_step",
+           "probe_step", "gamma_obj", "gamma_probe", "probe_update_start", "batch", "orthogonalize", "seed"]
+
+
+def params_pair(s, **kw):
+    """(C params, oracle Params) with identical settings for scan s."""
+    import paper_2406_06640_amd as P
+
+    base = dict(n=s["n"], n_modes=s["k"], geometry=s["geometry"], fresnel_px=float(s["fresnel_px"]),
+                sigma1=float(s["sigma"]), sigma2=float(s["sigma"]))
+    base.update(kw)
+    op = ora.Params(**{k: v for k, v in base.items() if k in _SHARED})
+    cp = P.default_params(n_pos=len(s["positions"]), obj_h=s["obj0"].shape[0], obj_w=s["obj0"].shape[1])
+    for name in _SHARED:
+        setattr(cp, name, getattr(op, name))
+    return cp, op
+
+
+def state32(s):
+    """Initial state rounded to complex64 (what the GPU holds), widened for the oracle."""
+    o = s["obj0"].astype(np.complex64)
+    p = s["probe0"].astype(np.complex64)
+    return o, p
+
+
+def gpu_step(s, cp, idx, t, obj=None, probe=None):
+    """One debug step on a fresh context; returns the captures and the updated state."""
+    import paper_2406_06640_amd as P
+
+    o32, p32 = state32(s)
+    if obj is not None:
+        o32 = obj.astype(np.complex64)
+    if probe is not None:
+        p32 = probe.astype(np.complex64)
+    n, k = cp.n, cp.n_modes
+    B = len(idx)
+    h, w = o32.shape
+    cap = dict(psi=np.zeros((B, k, n, n), np.complex64), psi_new=np.zeros((B, k, n, n), np.complex64),
+               factor=np.zeros((B, n, n), np.float32), n_obj=np.zeros((h, w), np.complex64),
+               w_obj=np.zeros((h, w), np.float32), n_probe=np.zeros((k, n, n), np.complex64),
+               v_probe=np.zeros((n, n), np.float32))
+    rec = P.Reconstruction(cp, s["intensities"], s["positions"], p32, o32)
+    try:
+        P.ptycho_debug_step(rec.ctx, idx, t, **cap)
+        cap["O"] = rec.object()
+        cap["P"] = rec.probe()
+    finally:
+        rec.close()
+    return cap, o32, p32
+
+
+def oracle_step(s, op, idx, t, o32, p32):
+    sq = ora.measured_amplitude(s["intensities"], op)
+    O, Pn, err, cap = ora.batch_step(o32.astype(np.complex128), p32.astype(np.complex128), sq, s["positions"],
+                                     list(idx), t, op, capture=True)
+    cap["O"] = O
+    cap["P"] = Pn
+    cap["err"] = err
+    return cap

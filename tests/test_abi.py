@@ -1,0 +1,100 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and its host-only logic (defaults, validation, the order generator) behaves as
+documented.  No GPU work is started here."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptycho.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptycho_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2406_06640_amd as P
+    lib = ctypes.CDLL(P.library_path())
+    names = _declared()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in ptycho.h but not exported"
+
+
+def test_defaults():
+    import paper_2406_06640_amd as P
+    p = P.default_params()
+    assert (p.n, p.n_modes, p.kernel_size, p.batch, p.probe_update_start) == (64, 1, 11, 1, 1)
+    assert p.sigma1 == 1.0 and p.sigma2 == 1.0 and p.alpha1 == 1.0 and p.alpha2 == 0.0
+    assert abs(p.eps - 1e-6) < 1e-12 and p.cc_start == 0 and p.gamma_obj == 1.0
+
+
+def test_permutation_matches_oracle_generator():
+    import oracle as ora
+    import paper_2406_06640_amd as P
+    for seed, t, n in [(0, 1, 10), (7, 3, 100), (2 ** 63 + 5, 17, 1600), (1, 1, 1), (1, 1, 0)]:
+        np.testing.assert_array_equal(P.ptycho_permutation(seed, t, n), ora.permutation(seed, t, n))
+
+
+def _params(**kw):
+    import paper_2406_06640_amd as P
+    base = dict(n=16, n_pos=2, obj_h=32, obj_w=32)
+    base.update(kw)
+    return P.default_params(**base)
+
+
+def _arrays(n=16, n_pos=2, obj=32, k=1):
+    inten = np.ones((n_pos, n, n), np.float32)
+    pos = np.array([[0, 0], [16, 16]], np.int32)[:n_pos]
+    probe = np.ones((k, n, n), np.complex64)
+    o = np.ones((obj, obj), np.complex64)
+    return inten, pos, probe, o
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=20), -1), (dict(n_modes=0), -1), (dict(n_modes=17), -1), (dict(kernel_size=10), -1),
+    (dict(kernel_size=33), -1), (dict(alpha1=1.5), -1), (dict(gamma_obj=0.0), -1), (dict(batch=0), -1),
+    (dict(batch=257), -1), (dict(cbar_min=0.0), -1), (dict(sigma1=-1.0), -1), (dict(geometry=1), -1),
+    (dict(obj_h=8), -1), (dict(sigma2=float("nan")), -1), (dict(orthogonalize=2), -1),
+])
+def test_invalid_parameters_rejected_before_device_work(kw, status):
+    import paper_2406_06640_amd as P
+    with pytest.raises(P.PtychoError) as ei:
+        P.ptycho_init(_params(**kw), *_arrays())
+    assert ei.value.status == status
+    assert P.ptycho_last_error(None)
+
+
+def test_bad_inputs_rejected():
+    import paper_2406_06640_amd as P
+    inten, pos, probe, o = _arrays()
+    bad_pos = pos.copy()
+    bad_pos[1] = [17, 0]  # box rows 17..32 fall outside a 32-row object
+    with pytest.raises(P.PtychoError) as ei:
+        P.ptycho_init(_params(), inten, bad_pos, probe, o)
+    assert ei.value.status == P.PTYCHO_E_SHAPE
+    nan_i = inten.copy()
+    nan_i[0, 3, 3] = np.nan
+    with pytest.raises(P.PtychoError) as ei:
+        P.ptycho_init(_params(), nan_i, pos, probe, o)
+    assert ei.value.status == P.PTYCHO_E_INVALID
+    with pytest.raises(P.PtychoError) as ei:
+        P.ptycho_init(_params(), inten, pos, np.zeros_like(probe), o)
+    assert ei.value.status == P.PTYCHO_E_INVALID and "zero power" in str(ei.value)
+
+
+def test_null_context_calls_fail_cleanly():
+    import paper_2406_06640_amd as P
+    lib = P.load_library()
+    assert lib.ptycho_iterate(None, 1, None, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_iteration(None) == -1
+    lib.ptycho_destroy(None)
+    assert P.ptycho_last_error(None)
+    assert lib.ptycho_kernel_name(999) is None
