@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the pc-ePIE hot path on one MI355X.
+
+Workload: the far-field 1024^2-object scan with 256^2 frames, a 40 x 40 raster
+at 16 px (1600 positions), K = 4 incoherent probe modes, 5-wavelength +-2.5 %
+polychromatic data blurred by sigma = 2 px with Poisson noise at 1e6 counts
+(synthetic, seeded).  One step = one full pc-ePIE iteration over all 1600
+positions in batches of 32: every pass of the method runs (exit waves,
+propagation, mode sum, Gaussian blur, modulus constraint, back-propagation,
+object/probe updates, the complex constraint, mode orthogonalisation, the
+data error).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  The metric is mode-pattern updates per second =
+positions x modes x steps / wall-seconds.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def per_slot_bytes(name, n, k):
+    """Algorithmic HBM bytes one batch slot (one scan position) costs in kernel `name`,
+    counting each frame read or written at its pass boundary once (complex64 = 8 B,
+    float = 4 B).  Probe reads are shared by the batch and left out."""
+    nn = n * n
+    return {
+        "fwd_rows": 8 * nn + 8 * k * nn,             # box gather in, K row-transformed frames out
+        "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, mode-sum intensity out
+        "blur_factor": 12 * nn,                      # intensity + measured amplitude in, factor out
+        "inv_cols": 16 * k * nn + 4 * nn,            # K frames in and out, factor in
+        "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
+        "probe_accum": 8 * k * nn + 8 * nn,          # K probe contributions in, box in
+    }.get(name)
+
+
+def build_workload(n_pos=None):
+    import datagen
+    spec = datagen.CONFIGS["c2"]
+    t0 = time.time()
+    s = datagen.make_scan(spec, 1002, n_pos=n_pos)
+    return spec, s, time.time() - t0
+
+
+def make_params(P, s, spec, batch):
+    cp = P.default_params(n=s["n"], n_modes=s["k"], n_pos=len(s["positions"]), obj_h=s["obj0"].shape[0],
+                          obj_w=s["obj0"].shape[1], geometry=s["geometry"], sigma1=spec["sigma"],
+                          sigma2=spec["sigma"], batch=batch, cc_start=1, cc_end=1 << 30, alpha1=1.0,
+                          alpha2=0.0, orthogonalize=1, seed=1)
+    return cp
+
+
+def cpu_baseline(s, spec, batch, n_batches):
+    """The FP64 oracle as it stands on the host cores: the first n_batches batches of one
+    iteration of the same workload, converted to mode-pattern updates/s."""
+    import oracle as ora
+    op = ora.Params(n=s["n"], n_modes=s["k"], sigma1=spec["sigma"], sigma2=spec["sigma"], batch=batch,
+                    cc_start=1, cc_end=1 << 30, seed=1)
+    sq = ora.measured_amplitude(s["intensities"], op)
+    order = ora.permutation(1, 1, len(s["positions"]))
+    O, Pm = s["obj0"].astype(np.complex128), s["probe0"].astype(np.complex128)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.time()
+    for b in range(n_batches):
+        O, Pm, _, _ = ora.batch_step(O, Pm, sq, s["positions"], list(order[b * batch:(b + 1) * batch]), 1, op)
+    wall = time.time() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    done = n_batches * batch * s["k"]
+    return {"value": done / wall, "unit": "mode-pattern updates/s", "cores": round(cpu / wall, 1),
+            "kind": "oracle", "sample": f"first {n_batches} batches of {batch} positions "
+            f"({n_batches * batch} of {len(s['positions'])} positions) of iteration 1, {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-batches", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2406_06640_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec, s, gen_s = build_workload()
+    print(f"[bench] workload generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    n, k, n_pos = s["n"], s["k"], len(s["positions"])
+    cp = make_params(P, s, spec, args.batch)
+
+    # inputs resident in HBM before the timed region
+    inten = torch.from_numpy(s["intensities"]).to(dev)
+    pos = torch.from_numpy(s["positions"]).to(dev)
+    probe0 = torch.from_numpy(s["probe0"].astype(np.complex64)).to(dev)
+    obj0 = torch.from_numpy(s["obj0"].astype(np.complex64)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    ctx = P.ptycho_init(cp, inten, pos, probe0, obj0, P.PTYCHO_MEM_DEVICE, stream)
+    names = P.kernel_names()
+    try:
+        P.ptycho_iterate(ctx, args.warmup)
+        # one profiled iteration (events around every launch) to find the dominant kernel
+        P.ptycho_set_timing(ctx, (1 << len(names)) - 1)
+        P.ptycho_iterate(ctx, 1)
+        P.ptycho_set_timing(ctx, 0)
+        prof = {nm: P.ptycho_kernel_time(ctx, i, reset=True) for i, nm in enumerate(names)}
+        dom = max(prof, key=lambda nm: prof[nm][0])
+        print("[bench] per-iteration kernel ms: " +
+              ", ".join(f"{nm}={ms:.3f}({c})" for nm, (ms, c) in prof.items() if c), file=sys.stderr, flush=True)
+        # timed region: HIP events around the dominant kernel only
+        P.ptycho_set_timing(ctx, 1 << names.index(dom))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs = P.ptycho_iterate(ctx, args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        P.ptycho_set_timing(ctx, 0)
+        dom_ms, dom_cnt = P.ptycho_kernel_time(ctx, names.index(dom), reset=True)
+    finally:
+        P.ptycho_destroy(ctx)
+
+    ms_per_step = 1e3 * wall / args.steps
+    value = n_pos * k * args.steps / wall
+    roof = None
+    pb = per_slot_bytes(dom, n, k)
+    if pb is not None and dom_cnt:
+        # every launch of a batch kernel processes one full batch except the ragged last one
+        slots_per_iter = n_pos
+        launches_per_iter = -(-n_pos // args.batch)
+        bytes_per_launch = pb * slots_per_iter / launches_per_iter
+        avg_s = dom_ms / dom_cnt / 1e3
+        achieved = bytes_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)}
+    out = {
+        "metric": "mode-pattern updates/s",
+        "value": round(value, 1),
+        "unit": "mode-pattern updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded forward model; see datagen/)",
+        "config": {"workload": "far field, object 1024x1024, frames 256x256, 40x40 raster at 16 px "
+                               "(1600 positions), K=4 modes, 5 wavelengths +-2.5%, sigma=2, Poisson 1e6; "
+                               f"pc-ePIE batch {args.batch}, 11x11 blur, complex constraint and "
+                               "orthogonalisation on every timed iteration",
+                   "positions": n_pos, "modes": k, "frame": n, "batch": args.batch},
+        "roofline": roof,
+        "kernel_ms_per_step": {nm: round(ms, 4) for nm, (ms, c) in prof.items() if c},
+        "final_data_error": float(errs[-1]),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(s, spec, args.batch, args.cpu_batches)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,7 +86,7 @@ def probe_modes(base, k, powers, total_power=1.0):
     y = (y - n / 2) / (n / 4)
     cols = np.stack([(base * _POLY[i](x, y)).ravel() for i in range(k)], axis=1)
     q, _ = np.linalg.qr(cols)
-    modes = q.T.reshape(k, n, n)
+    modes = np.ascontiguousarray(q.T).reshape(k, n, n)
     # fix the sign of each mode so it overlaps positively with its generator
     for i in range(k):
         ov = np.vdot(modes[i], base * _POLY[i](x, y))

@@ -123,8 +123,8 @@ def _ptr(x, dtype, mem_kind, keep):
     if _is_torch(x):
         if mem_kind != PTYCHO_MEM_DEVICE or not x.is_cuda:
             raise ValueError("torch tensors must be CUDA tensors passed with PTYCHO_MEM_DEVICE")
-        if not x.is_contiguous():
-            raise ValueError("torch tensor must be contiguous")
+        x = x.contiguous()
+        keep.append(x)
         return ctypes.c_void_p(x.data_ptr())
     if mem_kind != PTYCHO_MEM_HOST:
         raise ValueError("numpy arrays are host memory: use PTYCHO_MEM_HOST")
