@@ -38,9 +38,8 @@ def per_slot_bytes(name, n, k):
     nn = n * n
     return {
         "fwd_rows": 8 * nn + 8 * k * nn,             # box gather in, K row-transformed frames out
-        "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, mode-sum intensity out
-        "blur_factor": 12 * nn,                      # intensity + measured amplitude in, factor out
-        "inv_cols": 16 * k * nn + 4 * nn,            # K frames in and out, factor in
+        "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, vertically blurred amplitude out
+        "inv_cols": 16 * k * nn + 8 * nn,            # K frames in and out, blurred amplitude + measurement in
         "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
         "probe_accum": 8 * k * nn + 8 * nn,          # K probe contributions in, box in
     }.get(name)

@@ -173,4 +173,246 @@ __device__ __forceinline__ void fft_lines(float2* buf, int ld, const float2* tw)
   else static_assert(N == 8, "unsupported FFT length");
 }
 
+// ---------------------------------------------------------------------------
+// Register-fed transforms: the first stage reads its inputs through a Load
+// functor (global memory, with any elementwise prologue fused) and the last
+// stage hands its outputs to a Store functor, so only the middle stages use
+// LDS.  Lines are laid out in LDS by Frame<N, NL, LF>:
+//   LF = false: line-major   (a row pass: thread butterflies run along a line)
+//   LF = true : position-major (a column pass: consecutive threads take
+//               consecutive lines, i.e. adjacent columns of the frame, so
+//               global accesses are coalesced row segments)
+// Load(slot, line, pos) -> float2 and Store(slot, line, pos, float2) receive a
+// per-thread slot index (butterfly i, leg r) that is the same for every call
+// of the same transform shape, so callers can keep per-element registers.
+// ---------------------------------------------------------------------------
+
+template <int N, int NL, bool LF>
+struct Frame {
+  static constexpr int LD = LF ? NL + 1 : N + 1;
+  static constexpr int ELEMS = LF ? N * LD : NL * LD;
+  __device__ __forceinline__ static int lidx(int line, int pos) { return LF ? pos * LD + line : line * LD + pos; }
+  template <int M>
+  __device__ __forceinline__ static void map(int f, int& line, int& j) {
+    if (LF) {
+      line = f % NL;
+      j = f / NL;
+    } else {
+      line = f / M;
+      j = f - line * M;
+    }
+  }
+};
+
+template <int N, int R>
+struct StageShape {
+  static constexpr int M = N / R;
+};
+
+template <int N, int NL, int R>
+struct Slots {
+  static constexpr int TOT = NL * (N / R);
+  static constexpr int NB = (TOT + 255) / 256;
+  static constexpr int COUNT = NB * R;
+};
+
+template <int N, int NL, bool LF, bool INV, int R, int NS>
+__device__ __forceinline__ void mid_stage(float2* buf, const float2* __restrict__ tw) {
+  using F = Frame<N, NL, LF>;
+  constexpr int M = N / R;
+  constexpr int TOT = NL * M;
+  constexpr int NB = (TOT + 255) / 256;
+  float2 v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      int line, j;
+      F::template map<M>(f, line, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[F::lidx(line, j + r * M)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      int line, j;
+      F::template map<M>(f, line, j);
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[r * k * (N / (NS * R))];
+        v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+      }
+      Dft<R, INV>::run(v[i]);
+      const int idx = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[F::lidx(line, idx + r * NS)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Last stage: inputs from LDS, outputs to Store at positions j + r N/R.
+// STORE_LDS: the store writes back into `buf`, so all reads finish first.
+template <int N, int NL, bool LF, bool INV, bool STORE_LDS, int R, int NS, class Store>
+__device__ __forceinline__ void last_stage(float2* buf, const float2* __restrict__ tw, Store& store) {
+  using F = Frame<N, NL, LF>;
+  constexpr int M = N / R;
+  static_assert(NS == M, "last stage");
+  constexpr int TOT = NL * M;
+  constexpr int NB = (TOT + 255) / 256;
+  float2 v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      int line, j;
+      F::template map<M>(f, line, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[F::lidx(line, j + r * M)];
+    }
+  }
+  if (STORE_LDS) __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      int line, j;
+      F::template map<M>(f, line, j);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[r * j * (N / (NS * R))];
+        v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+      }
+      Dft<R, INV>::run(v[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(i * R + r, line, j + r * M, v[i][r]);
+    }
+  }
+}
+
+template <int N, int NL, bool LF, bool INV, bool STORE_LDS, class Store, int NS, int R, int... Rest>
+__device__ __forceinline__ void stages_from_lds(float2* buf, const float2* tw, Store& store) {
+  if constexpr (sizeof...(Rest) == 0) {
+    last_stage<N, NL, LF, INV, STORE_LDS, R, NS>(buf, tw, store);
+  } else {
+    mid_stage<N, NL, LF, INV, R, NS>(buf, tw);
+    stages_from_lds<N, NL, LF, INV, STORE_LDS, Store, NS * R, Rest...>(buf, tw, store);
+  }
+}
+
+// First stage (radix R0) fed by Load, remaining stages through LDS, last to Store.
+// LOAD_LDS: the loads read `buf`, so they all finish before stage 0 writes it.
+// On return the last stage's LDS reads are done but no barrier follows; a
+// caller that rewrites `buf` afterwards must synchronise first.
+template <int N, int NL, bool LF, bool INV, bool LOAD_LDS, bool STORE_LDS, class Load, class Store, int R0,
+          int... Rs>
+__device__ __forceinline__ void fft_reg_impl(float2* buf, const float2* __restrict__ tw, Load& load, Store& store) {
+  using F = Frame<N, NL, LF>;
+  constexpr int M = N / R0;
+  constexpr int TOT = NL * M;
+  constexpr int NB = (TOT + 255) / 256;
+  float2 v[NB][R0];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      int line, j;
+      F::template map<M>(f, line, j);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[i][r] = load(i * R0 + r, line, j + r * M);
+    }
+  }
+  if constexpr (sizeof...(Rs) == 0) {
+    if (LOAD_LDS && STORE_LDS) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int f = threadIdx.x + i * 256;
+      if (TOT % 256 == 0 || f < TOT) {
+        int line, j;
+        F::template map<M>(f, line, j);
+        Dft<R0, INV>::run(v[i]);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) store(i * R0 + r, line, j + r * M, v[i][r]);
+      }
+    }
+  } else {
+    if (LOAD_LDS) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int f = threadIdx.x + i * 256;
+      if (TOT % 256 == 0 || f < TOT) {
+        int line, j;
+        F::template map<M>(f, line, j);
+        Dft<R0, INV>::run(v[i]);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) buf[F::lidx(line, j * R0 + r)] = v[i][r];
+      }
+    }
+    __syncthreads();
+    stages_from_lds<N, NL, LF, INV, STORE_LDS, Store, R0, Rs...>(buf, tw, store);
+  }
+}
+
+// Radix plans (first radix, then the rest); the first and last radices set
+// the Load and Store slot shapes: FirstR<N>, LastR<N>.
+template <int N> struct Plan;
+template <> struct Plan<8> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<8, NL, LF, INV, LL, SL, L, S, 8>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 8; };
+template <> struct Plan<16> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<16, NL, LF, INV, LL, SL, L, S, 4, 4>(b, t, l, s); } static constexpr int FIRST = 4, LAST = 4; };
+template <> struct Plan<24> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<24, NL, LF, INV, LL, SL, L, S, 3, 8>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 8; };
+template <> struct Plan<32> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<32, NL, LF, INV, LL, SL, L, S, 8, 4>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 4; };
+template <> struct Plan<48> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<48, NL, LF, INV, LL, SL, L, S, 3, 4, 4>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 4; };
+template <> struct Plan<64> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<64, NL, LF, INV, LL, SL, L, S, 8, 8>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 8; };
+template <> struct Plan<96> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<96, NL, LF, INV, LL, SL, L, S, 3, 8, 4>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 4; };
+template <> struct Plan<128> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<128, NL, LF, INV, LL, SL, L, S, 8, 4, 4>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 4; };
+template <> struct Plan<192> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<192, NL, LF, INV, LL, SL, L, S, 3, 8, 8>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 8; };
+template <> struct Plan<256> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<256, NL, LF, INV, LL, SL, L, S, 4, 4, 4, 4>(b, t, l, s); } static constexpr int FIRST = 4, LAST = 4; };
+template <> struct Plan<384> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<384, NL, LF, INV, LL, SL, L, S, 3, 8, 4, 4>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 4; };
+template <> struct Plan<512> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<512, NL, LF, INV, LL, SL, L, S, 8, 8, 8>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 8; };
+template <> struct Plan<768> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<768, NL, LF, INV, LL, SL, L, S, 3, 4, 8, 8>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 8; };
+template <> struct Plan<1024> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<1024, NL, LF, INV, LL, SL, L, S, 4, 4, 8, 8>(b, t, l, s); } static constexpr int FIRST = 4, LAST = 8; };
+
+// Enumerate this thread's Load (first-stage) or Store (last-stage) slots:
+// fn(slot, line, pos) for every element the transform will hand it.
+template <int N, int NL, bool LF, int R, class Fn>
+__device__ __forceinline__ void for_slots(Fn&& fn) {
+  using F = Frame<N, NL, LF>;
+  constexpr int M = N / R;
+  constexpr int TOT = NL * M;
+  constexpr int NB = (TOT + 255) / 256;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      int line, j;
+      F::template map<M>(f, line, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) fn(i * R + r, line, j + r * M);
+    }
+  }
+}
+template <int N, int NL, bool LF, class Fn>
+__device__ __forceinline__ void for_load_slots(Fn&& fn) {
+  for_slots<N, NL, LF, Plan<N>::FIRST>(fn);
+}
+template <int N, int NL, bool LF, class Fn>
+__device__ __forceinline__ void for_store_slots(Fn&& fn) {
+  for_slots<N, NL, LF, Plan<N>::LAST>(fn);
+}
+
+// Register-fed transform of NL lines of length N.  Load and Store see slots
+// 0 .. LoadSlots-1 and 0 .. StoreSlots-1 respectively.
+template <int N, int NL, bool LF, bool INV, bool LOAD_LDS = false, bool STORE_LDS = false, class Load, class Store>
+__device__ __forceinline__ void fft_reg(float2* buf, const float2* tw, Load& load, Store& store) {
+  Plan<N>::template run<NL, LF, INV, LOAD_LDS, STORE_LDS>(buf, tw, load, store);
+}
+template <int N, int NL>
+struct RegShape {
+  static constexpr int LOAD_SLOTS = Slots<N, NL, Plan<N>::FIRST>::COUNT;
+  static constexpr int STORE_SLOTS = Slots<N, NL, Plan<N>::LAST>::COUNT;
+};
+
 }  // namespace pty

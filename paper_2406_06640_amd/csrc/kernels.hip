@@ -3,15 +3,17 @@
 // One batch of B scan positions, each with K incoherent probe modes, moves
 // through these passes (frames live in X[b][k][N][N], complex64):
 //   fwd_rows   psi = o_b P_k (box gather fused), 1D transform along x       (Eq. 1)
-//   fwd_cols   1D transform along y; I_mod = sum_k |Psi_k|^2                (mode sum)
-//   blur       A^G = sqrt(I_mod) (x) g  (or I_mod (x) g), factor, data error  (Eq. 6-7, box 1)
-//   inv_cols   Psi' = factor Psi, inverse 1D transform along y
+//   fwd_cols   1D transform along y; I_mod = sum_k |Psi_k|^2 (mode sum); vertical
+//              half of the Gaussian blur of sqrt(I_mod) (or I_mod)          (Eq. 6-7, box 1)
+//   inv_cols   horizontal half of the blur, modulus factor, data error;
+//              Psi' = factor Psi, inverse 1D transform along y
 //   inv_rows   inverse along x -> psi'; dpsi = psi' - o_b P_k; per-slot object
 //              numerator sum_k conj(P_k) dpsi_k; X <- conj(o_b) dpsi_k
 //   probe_acc  N_P,k = sum_b X[b][k] and V = sum_b |o_b|^2 in slot order
 //   obj_wmax / obj_update   W and N_O gathered per object tile in slot order; O update
+//                           (and, in constraint windows, the C-bar sums of Eq. 11)
 //   probe_update            P_k update; sum_k |P_k|^2 refreshed
-//   cc_sums / cc_apply      complex constraint, Eq. (9)-(11) (box 2)
+//   cc_apply                complex constraint, Eq. (9)-(10) (box 2)
 // Near-field frames use the separable paraxial transfer function: each 1D
 // pass is forward FFT, multiply by h, inverse FFT.  Every reduction runs in a
 // fixed order (no atomics), so results are bitwise reproducible.
@@ -24,8 +26,8 @@
 namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
-    "fwd_rows", "fwd_cols", "blur_factor", "inv_cols", "inv_rows_update", "probe_accum", "obj_wmax",
-    "obj_update", "probe_update", "cc_sums", "cc_apply", "gram", "eig", "mode_remix", "err_reduce"};
+    "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "probe_accum", "obj_wmax",
+    "obj_update", "probe_update", "cc_apply", "gram", "eig", "mode_remix", "err_reduce"};
 
 constexpr int kThreads = 256;
 
@@ -74,32 +76,19 @@ __device__ __forceinline__ float block_max_f(float v, float* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// Row passes
+// Row passes (lines along x; Frame<N, L, false>)
 // ---------------------------------------------------------------------------
-
-// After fft_lines, apply the near-field transfer function (conjugated for the
-// inverse direction) and the inverse transform, so `a` ends as F^-1 h F of the
-// input line (unnormalised by N).
-template <int N, int NL, bool CONJ>
-__device__ __forceinline__ void near_mid(float2* a, int ld, const float2* tw, const float2* __restrict__ h) {
-  for (int e = threadIdx.x; e < NL * N; e += kThreads) {
-    const int l = e / N, x = e - l * N;
-    const float2 hv = h[x];
-    a[l * ld + x] = CONJ ? cmulc(a[l * ld + x], hv) : cmul(a[l * ld + x], hv);
-  }
-  __syncthreads();
-  fft_lines<N, NL, true>(a, ld, tw);
-}
 
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                        int ns) {
-  constexpr int L = Cfg<N>::ROWS, LD = Cfg<N>::LD;
-  constexpr int E = (L * N + kThreads - 1) / kThreads;
+  constexpr int L = Cfg<N>::ROWS;
+  using F = Frame<N, L, false>;
+  constexpr int LS = RegShape<N, L>::LOAD_SLOTS;
   extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* hn = sm + N;
-  float2* bufA = sm + 2 * N;
+  float2* buf = sm + 2 * N;
   const int b = blockIdx.y;
   if (b >= ns) return;
   const int y0 = blockIdx.x * L;
@@ -108,38 +97,24 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, c
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
-  float2 o[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = threadIdx.x + i * kThreads;
-    if (e < L * N) {
-      const int ly = e / N, x = e - ly * N;
-      o[i] = d.obj[(size_t)(rc.x + y0 + ly) * p.w_obj + rc.y + x];
-    }
-  }
+  float2 o[LS];
+  for_load_slots<N, L, false>([&](int s, int line, int pos) {
+    o[s] = d.obj[(size_t)(rc.x + y0 + line) * p.w_obj + rc.y + pos];
+  });
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   for (int k = 0; k < p.k; ++k) {
-    const float2* pk = d.probe + (size_t)k * N * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < L * N) {
-        const int ly = e / N, x = e - ly * N;
-        bufA[ly * LD + x] = cmul(o[i], pk[(y0 + ly) * N + x]);
-      }
-    }
-    __syncthreads();
-    float2* a = bufA;
-    fft_lines<N, L, false>(a, LD, tw);
-    if (NEAR) near_mid<N, L, false>(a, LD, tw, hn);
+    const float2* pk = d.probe + (size_t)k * N * N + (size_t)y0 * N;
     float2* out = d.X + ((size_t)(b * p.k + k) * N + y0) * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < L * N) {
-        const int ly = e / N, x = e - ly * N;
-        out[ly * N + x] = cscale(a[ly * LD + x], scale);
-      }
+    auto load = [&](int s, int line, int pos) { return cmul(o[s], pk[line * N + pos]); };
+    auto store = [&](int s, int line, int pos, float2 v) { out[line * N + pos] = cscale(v, scale); };
+    if (!NEAR) {
+      fft_reg<N, L, false, false>(buf, tw, load, store);
+    } else {
+      auto to_lds = [&](int s, int line, int pos, float2 v) { buf[F::lidx(line, pos)] = cmul(v, hn[pos]); };
+      auto from_lds = [&](int s, int line, int pos) { return buf[F::lidx(line, pos)]; };
+      fft_reg<N, L, false, false, false, true>(buf, tw, load, to_lds);
+      __syncthreads();
+      fft_reg<N, L, false, true, true, false>(buf, tw, from_lds, store);
     }
     __syncthreads();
   }
@@ -148,12 +123,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, c
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                        int ns, DebugPtrs dbg) {
-  constexpr int L = Cfg<N>::ROWS, LD = Cfg<N>::LD;
-  constexpr int E = (L * N + kThreads - 1) / kThreads;
+  constexpr int L = Cfg<N>::ROWS;
+  using F = Frame<N, L, false>;
+  constexpr int SS = RegShape<N, L>::STORE_SLOTS;
   extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* hn = sm + N;
-  float2* bufA = sm + 2 * N;
+  float2* buf = sm + 2 * N;
   const int b = blockIdx.y;
   if (b >= ns) return;
   const int y0 = blockIdx.x * L;
@@ -162,71 +138,62 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, c
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
-  float2 o[E], acc[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = threadIdx.x + i * kThreads;
-    acc[i] = make_float2(0.f, 0.f);
-    if (e < L * N) {
-      const int ly = e / N, x = e - ly * N;
-      o[i] = d.obj[(size_t)(rc.x + y0 + ly) * p.w_obj + rc.y + x];
-    }
-  }
+  float2 o[SS], acc[SS];
+  for_store_slots<N, L, false>([&](int s, int line, int pos) {
+    o[s] = d.obj[(size_t)(rc.x + y0 + line) * p.w_obj + rc.y + pos];
+    acc[s] = make_float2(0.f, 0.f);
+  });
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   for (int k = 0; k < p.k; ++k) {
     float2* fr = d.X + ((size_t)(b * p.k + k) * N + y0) * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < L * N) {
-        const int ly = e / N, x = e - ly * N;
-        bufA[ly * LD + x] = fr[ly * N + x];
-      }
-    }
-    __syncthreads();
-    float2* a = bufA;
-    if (NEAR) {
-      fft_lines<N, L, false>(a, LD, tw);
-      near_mid<N, L, true>(a, LD, tw, hn);
+    const float2* pk = d.probe + (size_t)k * N * N + (size_t)y0 * N;
+    float2* dbgp = dbg.psi_new ? dbg.psi_new + ((size_t)(b * p.k + k) * N + y0) * N : nullptr;
+    auto load = [&](int s, int line, int pos) { return fr[line * N + pos]; };
+    auto store = [&](int s, int line, int pos, float2 v) {
+      const float2 psi_new = cscale(v, scale);
+      const float2 pv = pk[line * N + pos];
+      const float2 dpsi = csub(psi_new, cmul(o[s], pv));
+      acc[s] = cadd(acc[s], cmulc(dpsi, pv));  // conj(P) dpsi
+      fr[line * N + pos] = cmulc(dpsi, o[s]);    // conj(o) dpsi
+      if (dbgp) dbgp[line * N + pos] = psi_new;
+    };
+    if (!NEAR) {
+      fft_reg<N, L, false, true>(buf, tw, load, store);
     } else {
-      fft_lines<N, L, true>(a, LD, tw);
-    }
-    const float2* pk = d.probe + (size_t)k * N * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < L * N) {
-        const int ly = e / N, x = e - ly * N;
-        const float2 psi_new = cscale(a[ly * LD + x], scale);
-        const float2 pv = pk[(y0 + ly) * N + x];
-        const float2 dpsi = csub(psi_new, cmul(o[i], pv));
-        acc[i] = cadd(acc[i], cmulc(dpsi, pv));  // conj(P) dpsi
-        fr[ly * N + x] = cmulc(dpsi, o[i]);       // conj(o) dpsi
-        if (dbg.psi_new) dbg.psi_new[((size_t)(b * p.k + k) * N + y0 + ly) * N + x] = psi_new;
-      }
+      auto to_lds = [&](int s, int line, int pos, float2 v) { buf[F::lidx(line, pos)] = cmulc(v, hn[pos]); };
+      auto from_lds = [&](int s, int line, int pos) { return buf[F::lidx(line, pos)]; };
+      fft_reg<N, L, false, false, false, true>(buf, tw, load, to_lds);
+      __syncthreads();
+      fft_reg<N, L, false, true, true, false>(buf, tw, from_lds, store);
     }
     __syncthreads();
   }
   float2* dO = d.dO + ((size_t)b * N + y0) * N;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = threadIdx.x + i * kThreads;
-    if (e < L * N) dO[e] = acc[i];
-  }
+  for_store_slots<N, L, false>([&](int s, int line, int pos) { dO[line * N + pos] = acc[s]; });
 }
 
 // ---------------------------------------------------------------------------
-// Column passes
+// Column passes (lines along y; Frame<N, C, true>: adjacent threads take
+// adjacent columns, so every global access is a coalesced row segment)
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ int wrap(int t, int n) {
+  t += (t < 0) ? n : 0;
+  return t - ((t >= n) ? n : 0);
+}
+
+// Forward column transform of every mode, the incoherent mode sum, and the
+// vertical (sigma2) half of the separable Gaussian blur of Eq. (6) (or of the
+// intensity, Eq. 2): q = g_y (x) sqrt(sum_k |Psi_k|^2).
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, int ns) {
-  constexpr int C = Cfg<N>::COLS, LD = Cfg<N>::LD;
-  constexpr int E = (C * N + kThreads - 1) / kThreads;
+  constexpr int C = Cfg<N>::COLS;
+  using F = Frame<N, C, true>;
+  constexpr int SS = RegShape<N, C>::STORE_SLOTS;
   extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* hn = sm + N;
-  float2* bufA = sm + 2 * N;
+  float2* buf = sm + 2 * N;
   const int b = blockIdx.y;
   if (b >= ns) return;
   const int x0 = blockIdx.x * C;
@@ -234,162 +201,113 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, i
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
-  float acc[E];
+  float acc[SS];
 #pragma unroll
-  for (int i = 0; i < E; ++i) acc[i] = 0.f;
+  for (int i = 0; i < SS; ++i) acc[i] = 0.f;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   for (int k = 0; k < p.k; ++k) {
-    float2* fr = d.X + (size_t)(b * p.k + k) * N * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < C * N) {
-        const int y = e / C, c = e - y * C;
-        bufA[c * LD + y] = fr[(size_t)y * N + x0 + c];
-      }
-    }
-    __syncthreads();
-    float2* a = bufA;
-    fft_lines<N, C, false>(a, LD, tw);
-    if (NEAR) near_mid<N, C, false>(a, LD, tw, hn);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < C * N) {
-        const int y = e / C, c = e - y * C;
-        const float2 v = cscale(a[c * LD + y], scale);
-        fr[(size_t)y * N + x0 + c] = v;
-        acc[i] += v.x * v.x + v.y * v.y;
-      }
-    }
-    __syncthreads();
-  }
-  float* q = d.q + (size_t)b * N * N;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = threadIdx.x + i * kThreads;
-    if (e < C * N) {
-      const int y = e / C, c = e - y * C;
-      q[(size_t)y * N + x0 + c] = acc[i];
-    }
-  }
-}
-
-template <int N, bool NEAR>
-__global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, int ns) {
-  constexpr int C = Cfg<N>::COLS, LD = Cfg<N>::LD;
-  constexpr int E = (C * N + kThreads - 1) / kThreads;
-  extern __shared__ float2 sm[];
-  float2* tw = sm;
-  float2* hn = sm + N;
-  float2* bufA = sm + 2 * N;
-  const int b = blockIdx.y;
-  if (b >= ns) return;
-  const int x0 = blockIdx.x * C;
-  for (int i = threadIdx.x; i < N; i += kThreads) {
-    tw[i] = d.tw[i];
-    if (NEAR) hn[i] = d.hnear[i];
-  }
-  float f[E];
-  const float* fac = d.fac + (size_t)b * N * N;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = threadIdx.x + i * kThreads;
-    f[i] = 0.f;
-    if (e < C * N) {
-      const int y = e / C, c = e - y * C;
-      f[i] = fac[(size_t)y * N + x0 + c];
-    }
-  }
-  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  for (int k = 0; k < p.k; ++k) {
-    float2* fr = d.X + (size_t)(b * p.k + k) * N * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < C * N) {
-        const int y = e / C, c = e - y * C;
-        bufA[c * LD + y] = cscale(fr[(size_t)y * N + x0 + c], f[i]);
-      }
-    }
-    __syncthreads();
-    float2* a = bufA;
-    if (NEAR) {
-      fft_lines<N, C, false>(a, LD, tw);
-      near_mid<N, C, true>(a, LD, tw, hn);
+    float2* fr = d.X + (size_t)(b * p.k + k) * N * N + x0;
+    auto load = [&](int s, int c, int y) { return fr[(size_t)y * N + c]; };
+    auto store = [&](int s, int c, int y, float2 v) {
+      v = cscale(v, scale);
+      fr[(size_t)y * N + c] = v;
+      acc[s] += v.x * v.x + v.y * v.y;
+    };
+    if (!NEAR) {
+      fft_reg<N, C, true, false>(buf, tw, load, store);
     } else {
-      fft_lines<N, C, true>(a, LD, tw);
-    }
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < C * N) {
-        const int y = e / C, c = e - y * C;
-        fr[(size_t)y * N + x0 + c] = cscale(a[c * LD + y], scale);
-      }
+      auto to_lds = [&](int s, int c, int y, float2 v) { buf[F::lidx(c, y)] = cmul(v, hn[y]); };
+      auto from_lds = [&](int s, int c, int y) { return buf[F::lidx(c, y)]; };
+      fft_reg<N, C, true, false, false, true>(buf, tw, load, to_lds);
+      __syncthreads();
+      fft_reg<N, C, true, true, true, false>(buf, tw, from_lds, store);
     }
     __syncthreads();
   }
+  // vertical blur of the modelled amplitude (or intensity) over whole columns
+  float* tile = reinterpret_cast<float*>(buf);
+  constexpr int TS = C + 1;
+  for_store_slots<N, C, true>([&](int s, int c, int y) {
+    tile[y * TS + c] = p.blur_intensity ? acc[s] : sqrtf(acc[s]);
+  });
+  __syncthreads();
+  float* q = d.q + (size_t)b * N * N + x0;
+  const int h = p.ks_half;
+  for_store_slots<N, C, true>([&](int s, int c, int y) {
+    float g = p.gy[0] * tile[y * TS + c];
+    for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
+    q[(size_t)y * N + c] = g;
+  });
 }
 
-// ---------------------------------------------------------------------------
-// Box 1: Gaussian blur of the modelled amplitude and the modulus factor
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kThreads) void k_blur_factor(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                          int ns, int tb) {
-  constexpr int S = kBlurTile + 2 * kMaxHalf;
-  __shared__ float qs[S][S + 1];
-  __shared__ float hs[S][kBlurTile + 1];
+// Horizontal (sigma1) half of the blur, the modulus factor of box 1 and the
+// data error, then Psi' = factor Psi and the inverse column transform.
+template <int N, bool NEAR>
+__global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, const int* __restrict__ slots,
+                                                       int ns, DebugPtrs dbg) {
+  constexpr int C = Cfg<N>::COLS;
+  using F = Frame<N, C, true>;
+  constexpr int LS = RegShape<N, C>::LOAD_SLOTS;
+  extern __shared__ float2 sm[];
   __shared__ double red[kThreads];
-  const int b = blockIdx.z;
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* buf = sm + 2 * N;
+  const int b = blockIdx.y;
   if (b >= ns) return;
-  const int n = p.n, h = p.ks_half;
-  const int ty0 = blockIdx.y * tb, tx0 = blockIdx.x * tb;
-  const int s = tb + 2 * h;
-  const float* q = d.q + (size_t)b * n * n;
-  for (int e = threadIdx.x; e < s * s; e += kThreads) {
-    const int yy = e / s, xx = e - yy * s;
-    int gy = ty0 - h + yy, gx = tx0 - h + xx;
-    gy = ((gy % n) + n) % n;
-    gx = ((gx % n) + n) % n;
-    const float v = q[(size_t)gy * n + gx];
-    qs[yy][xx] = p.blur_intensity ? v : sqrtf(v);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < s * tb; e += kThreads) {
-    const int yy = e / tb, x = e - yy * tb;
-    float acc = p.gx[0] * qs[yy][x + h];
-    for (int dx = 1; dx <= h; ++dx) acc += p.gx[dx] * (qs[yy][x + h - dx] + qs[yy][x + h + dx]);
-    hs[yy][x] = acc;
-  }
-  __syncthreads();
+  const int x0 = blockIdx.x * C;
   const int pat = slots[b];
-  const float* amp = d.amp + (size_t)pat * n * n;
-  float* fac = d.fac + (size_t)b * n * n;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  const int h = p.ks_half;
+  const int TW = C + 2 * h;
+  float* tile = reinterpret_cast<float*>(buf);
+  const float* q = d.q + (size_t)b * N * N;
+  for (int e = threadIdx.x; e < N * TW; e += kThreads) {
+    const int y = e / TW, cc = e - y * TW;
+    tile[e] = q[(size_t)y * N + wrap(x0 - h + cc, N)];
+  }
+  __syncthreads();
+  float f[LS];
   double err = 0.0;
-  for (int e = threadIdx.x; e < tb * tb; e += kThreads) {
-    const int y = e / tb, x = e - y * tb;
-    float g = p.gy[0] * hs[y + h][x];
-    for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (hs[y + h - dy][x] + hs[y + h + dy][x]);
-    const size_t idx = (size_t)(ty0 + y) * n + tx0 + x;
-    const float a = amp[idx];
-    float ag, f;
+  const float* amp = d.amp + (size_t)pat * N * N + x0;
+  float* dbgf = dbg.factor ? dbg.factor + (size_t)b * N * N + x0 : nullptr;
+  for_load_slots<N, C, true>([&](int s, int c, int y) {
+    const float* row = tile + y * TW + c + h;
+    float g = p.gx[0] * row[0];
+    for (int dx = 1; dx <= h; ++dx) g += p.gx[dx] * (row[-dx] + row[dx]);
+    const float a = amp[(size_t)y * N + c];
+    float ag;
     if (p.blur_intensity) {
       ag = sqrtf(g);
-      f = a / sqrtf(g + p.eps * p.eps);
+      f[s] = a / sqrtf(g + p.eps * p.eps);
     } else {
       ag = g;
-      f = a / (g + p.eps);
+      f[s] = a / (g + p.eps);
     }
-    fac[idx] = f;
+    if (dbgf) dbgf[(size_t)y * N + c] = f[s];
     const double dd = (double)a - (double)ag;
     err += dd * dd;
-  }
-  const double tot = block_sum_d(err, red);
-  if (threadIdx.x == 0) {
-    const int tiles_x = n / tb;
-    d.err_part[(size_t)pat * tiles_x * tiles_x + blockIdx.y * tiles_x + blockIdx.x] = tot;
+  });
+  const double tot = block_sum_d(err, red);  // also orders the tile reads before the FFT's LDS writes
+  if (threadIdx.x == 0) d.err_part[(size_t)pat * (N / C) + blockIdx.x] = tot;
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  for (int k = 0; k < p.k; ++k) {
+    float2* fr = d.X + (size_t)(b * p.k + k) * N * N + x0;
+    auto load = [&](int s, int c, int y) { return cscale(fr[(size_t)y * N + c], f[s]); };
+    auto store = [&](int s, int c, int y, float2 v) { fr[(size_t)y * N + c] = cscale(v, scale); };
+    if (!NEAR) {
+      fft_reg<N, C, true, true>(buf, tw, load, store);
+    } else {
+      auto to_lds = [&](int s, int c, int y, float2 v) { buf[F::lidx(c, y)] = cmulc(v, hn[y]); };
+      auto from_lds = [&](int s, int c, int y) { return buf[F::lidx(c, y)]; };
+      fft_reg<N, C, true, false, false, true>(buf, tw, load, to_lds);
+      __syncthreads();
+      fft_reg<N, C, true, true, true, false>(buf, tw, from_lds, store);
+    }
+    __syncthreads();
   }
 }
 
@@ -397,28 +315,51 @@ __global__ __launch_bounds__(kThreads) void k_blur_factor(DevParams p, DevBufs d
 // Probe numerator / weight, object gather and updates
 // ---------------------------------------------------------------------------
 
+// blockIdx.y < K: N_P,k(pix) = sum_b X[b][k][pix]; blockIdx.y == K: V(pix) = sum_b |o_b(pix)|^2
+// and its per-block maximum.  Slots are summed in ascending order (4 running
+// sums over b mod 4, combined in a fixed tree).
 __global__ __launch_bounds__(kThreads) void k_probe_accum(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                           int ns) {
   __shared__ int2 bp[kMaxBatch];
   __shared__ float red[kThreads];
   const int n = p.n;
+  const size_t nn = (size_t)n * n;
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  const int k = blockIdx.y;
+  if (k < p.k) {
+    if (pix >= n * n) return;
+    const float2* x = d.X + (size_t)k * nn + pix;
+    const size_t st = (size_t)p.k * nn;
+    float2 s0 = make_float2(0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
+    int b = 0;
+    for (; b + 4 <= ns; b += 4) {
+      s0 = cadd(s0, x[(size_t)b * st]);
+      s1 = cadd(s1, x[(size_t)(b + 1) * st]);
+      s2 = cadd(s2, x[(size_t)(b + 2) * st]);
+      s3 = cadd(s3, x[(size_t)(b + 3) * st]);
+    }
+    for (; b < ns; ++b) s0 = cadd(s0, x[(size_t)b * st]);
+    d.nP[(size_t)k * nn + pix] = cadd(cadd(s0, s1), cadd(s2, s3));
+    return;
+  }
   for (int b = threadIdx.x; b < ns; b += kThreads) bp[b] = d.pos[slots[b]];
   __syncthreads();
-  const int pix = blockIdx.x * kThreads + threadIdx.x;
   float vmax = 0.f;
   if (pix < n * n) {
     const int y = pix / n, x = pix - y * n;
-    const size_t nn = (size_t)n * n;
-    for (int k = 0; k < p.k; ++k) {
-      float2 s = make_float2(0.f, 0.f);
-      for (int b = 0; b < ns; ++b) s = cadd(s, d.X[(size_t)(b * p.k + k) * nn + pix]);
-      d.nP[(size_t)k * nn + pix] = s;
+    float v0 = 0.f, v1 = 0.f;
+    int b = 0;
+    for (; b + 2 <= ns; b += 2) {
+      const float2 o0 = d.obj[(size_t)(bp[b].x + y) * p.w_obj + bp[b].y + x];
+      const float2 o1 = d.obj[(size_t)(bp[b + 1].x + y) * p.w_obj + bp[b + 1].y + x];
+      v0 += o0.x * o0.x + o0.y * o0.y;
+      v1 += o1.x * o1.x + o1.y * o1.y;
     }
-    float v = 0.f;
-    for (int b = 0; b < ns; ++b) {
-      const float2 o = d.obj[(size_t)(bp[b].x + y) * p.w_obj + bp[b].y + x];
-      v += o.x * o.x + o.y * o.y;
+    if (b < ns) {
+      const float2 o0 = d.obj[(size_t)(bp[b].x + y) * p.w_obj + bp[b].y + x];
+      v0 += o0.x * o0.x + o0.y * o0.y;
     }
+    const float v = v0 + v1;
     d.V[pix] = v;
     vmax = v;
   }
@@ -426,33 +367,49 @@ __global__ __launch_bounds__(kThreads) void k_probe_accum(DevParams p, DevBufs d
   if (threadIdx.x == 0) d.maxv_part[blockIdx.x] = m;
 }
 
-// Mark the slots whose boxes intersect this object tile; returns whether any does.
-__device__ __forceinline__ bool tile_hits(const DevBufs& d, const int* slots, int ns, int n, int r0, int c0,
-                                          int r1, int c1, int2* bp, int* hit, int* any) {
-  if (threadIdx.x == 0) *any = 0;
-  __syncthreads();
-  for (int b = threadIdx.x; b < ns; b += kThreads) {
-    const int2 rc = d.pos[slots[b]];
-    bp[b] = rc;
-    const int h = (rc.x < r1 && rc.x + n > r0 && rc.y < c1 && rc.y + n > c0) ? 1 : 0;
-    hit[b] = h;
-    if (h) *any = 1;  // benign: every writer stores 1
+// Ascending list of the slots whose boxes intersect the object tile
+// [r0, r0+T) x [c0, c0+T); returns the list length (uniform).  ns <= 256.
+struct TileList {
+  int2 pos[kMaxBatch];
+  int slot[kMaxBatch];
+  int cnt[kThreads / 64];
+};
+
+__device__ __forceinline__ int tile_list(const DevBufs& d, const int* slots, int ns, int n, int r0, int c0,
+                                         TileList& tl) {
+  const int b = threadIdx.x;
+  int2 rc = make_int2(0, 0);
+  bool hit = false;
+  if (b < ns) {
+    rc = d.pos[slots[b]];
+    hit = rc.x < r0 + kObjTile && rc.x + n > r0 && rc.y < c0 + kObjTile && rc.y + n > c0;
   }
+  const unsigned long long m = __ballot(hit);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) tl.cnt[w] = __popcll(m);
   __syncthreads();
-  return *any != 0;
+  int off = 0;
+  for (int i = 0; i < w; ++i) off += tl.cnt[i];
+  if (hit) {
+    const int at = off + __popcll(m & ((1ull << lane) - 1ull));
+    tl.slot[at] = b;
+    tl.pos[at] = rc;
+  }
+  int total = 0;
+  for (int i = 0; i < kThreads / 64; ++i) total += tl.cnt[i];
+  __syncthreads();
+  return total;
 }
 
 __global__ __launch_bounds__(kThreads) void k_obj_wmax(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                        int ns) {
-  __shared__ int2 bp[kMaxBatch];
-  __shared__ int hit[kMaxBatch];
-  __shared__ int any;
+  __shared__ TileList tl;
   __shared__ float red[kThreads];
   const int n = p.n;
   const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-  const bool touched = tile_hits(d, slots, ns, n, r0, c0, r0 + kObjTile, c0 + kObjTile, bp, hit, &any);
-  if (!touched) {
+  const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
+  if (cnt == 0) {
     if (threadIdx.x == 0) d.maxw_part[tile] = 0.f;
     return;
   }
@@ -461,10 +418,9 @@ __global__ __launch_bounds__(kThreads) void k_obj_wmax(DevParams p, DevBufs d, c
     const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
     if (r >= p.h_obj || c >= p.w_obj) continue;
     float w = 0.f;
-    for (int b = 0; b < ns; ++b) {
-      if (!hit[b]) continue;
-      const int yy = r - bp[b].x, xx = c - bp[b].y;
-      if (yy >= 0 && yy < n && xx >= 0 && xx < n) w += d.pw[yy * n + xx];
+    for (int i = 0; i < cnt; ++i) {
+      const int yy = r - tl.pos[i].x, xx = c - tl.pos[i].y;
+      if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) w += d.pw[yy * n + xx];
     }
     m = fmaxf(m, w);
   }
@@ -478,47 +434,63 @@ __device__ __forceinline__ float reduce_max_parts(const float* parts, int count,
   return block_max_f(m, red);
 }
 
+// Object update (gathered per tile, slots in ascending order).  Inside a
+// constraint window it also writes this tile's share of the C-bar sums of
+// Eq. (11): each pixel counted once per box that covers it.
 __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                         int ns, DebugPtrs dbg) {
-  __shared__ int2 bp[kMaxBatch];
-  __shared__ int hit[kMaxBatch];
-  __shared__ int any;
+                                                         int ns, int cc_sums, DebugPtrs dbg) {
+  __shared__ TileList tl;
   __shared__ float red[kThreads];
+  __shared__ double redd[kThreads];
   const int n = p.n;
   const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
-  const bool touched = tile_hits(d, slots, ns, n, r0, c0, r0 + kObjTile, c0 + kObjTile, bp, hit, &any);
-  if (!touched) return;
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
+  if (cnt == 0) {
+    if (cc_sums && threadIdx.x == 0) d.cc_part[tile] = make_double2(0.0, 0.0);
+    return;
+  }
   const float maxw = reduce_max_parts(d.maxw_part, gridDim.x * gridDim.y, red);
   const size_t nn = (size_t)n * n;
+  float sa = 0.f, sp = 0.f;
   for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
     const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
     if (r >= p.h_obj || c >= p.w_obj) continue;
     float w = 0.f;
     float2 num = make_float2(0.f, 0.f);
-    bool cov = false;
-    for (int b = 0; b < ns; ++b) {
-      if (!hit[b]) continue;
-      const int yy = r - bp[b].x, xx = c - bp[b].y;
-      if (yy >= 0 && yy < n && xx >= 0 && xx < n) {
+    int mult = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const int yy = r - tl.pos[i].x, xx = c - tl.pos[i].y;
+      if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) {
         w += d.pw[yy * n + xx];
-        num = cadd(num, d.dO[(size_t)b * nn + yy * n + xx]);
-        cov = true;
+        num = cadd(num, d.dO[(size_t)tl.slot[i] * nn + yy * n + xx]);
+        ++mult;
       }
     }
-    if (!cov) continue;
+    if (!mult) continue;
     const size_t oi = (size_t)r * p.w_obj + c;
     if (dbg.n_obj) {
       dbg.n_obj[oi] = num;
       dbg.w_obj[oi] = w;
     }
+    float2 o = d.obj[oi];
     const float den = (1.0f - p.gamma_obj) * w + p.gamma_obj * maxw;
     if (den > 0.f) {
       const float s = p.obj_step / den;
-      float2 o = d.obj[oi];
       o.x += s * num.x;
       o.y += s * num.y;
       d.obj[oi] = o;
     }
+    if (cc_sums) {
+      const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
+      sa += mult * fabsf(logf(a));
+      sp += mult * fabsf(atan2f(o.y, o.x));
+    }
+  }
+  if (cc_sums) {
+    const double ta = block_sum_d((double)sa, redd);
+    const double tp = block_sum_d((double)sp, redd);
+    if (threadIdx.x == 0) d.cc_part[tile] = make_double2(ta, tp);
   }
 }
 
@@ -559,43 +531,20 @@ __global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
 }
 
 // ---------------------------------------------------------------------------
-// Box 2: complex constraint, Eq. (9)-(11)
+// Box 2: complex constraint, Eq. (9)-(11), over the union of the batch boxes
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_cc_sums(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                      int ns) {
-  __shared__ double red[kThreads];
-  const int b = blockIdx.y;
-  if (b >= ns) return;
-  const int n = p.n;
-  const int2 rc = d.pos[slots[b]];
-  const int base = blockIdx.x * kCcChunk;
-  float sa = 0.f, sp = 0.f;
-  for (int e = base + threadIdx.x; e < base + kCcChunk && e < n * n; e += kThreads) {
-    const int y = e / n, x = e - y * n;
-    const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
-    const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
-    sa += fabsf(logf(a));
-    sp += fabsf(atan2f(o.y, o.x));
-  }
-  const double ta = block_sum_d((double)sa, red);
-  const double tp = block_sum_d((double)sp, red);
-  if (threadIdx.x == 0) d.cc_part[(size_t)b * gridDim.x + blockIdx.x] = make_double2(ta, tp);
-}
-
 __global__ __launch_bounds__(kThreads) void k_cc_apply(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns, int nchunks) {
-  __shared__ int2 bp[kMaxBatch];
-  __shared__ int hit[kMaxBatch];
-  __shared__ int any;
+                                                       int ns) {
+  __shared__ TileList tl;
   __shared__ double red[kThreads];
   const int n = p.n;
   const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
-  const bool touched = tile_hits(d, slots, ns, n, r0, c0, r0 + kObjTile, c0 + kObjTile, bp, hit, &any);
-  if (!touched) return;
+  const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
+  if (cnt == 0) return;
   double sa = 0.0, sp = 0.0;
-  const int cnt = ns * nchunks;
-  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+  const int parts = gridDim.x * gridDim.y;
+  for (int i = threadIdx.x; i < parts; i += kThreads) {
     sa += d.cc_part[i].x;
     sp += d.cc_part[i].y;
   }
@@ -609,10 +558,9 @@ __global__ __launch_bounds__(kThreads) void k_cc_apply(DevParams p, DevBufs d, c
     const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
     if (r >= p.h_obj || c >= p.w_obj) continue;
     bool cov = false;
-    for (int b = 0; b < ns && !cov; ++b) {
-      if (!hit[b]) continue;
-      const int yy = r - bp[b].x, xx = c - bp[b].y;
-      cov = (yy >= 0 && yy < n && xx >= 0 && xx < n);
+    for (int i = 0; i < cnt && !cov; ++i) {
+      const int yy = r - tl.pos[i].x, xx = c - tl.pos[i].y;
+      cov = (unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n;
     }
     if (!cov) continue;
     const size_t oi = (size_t)r * p.w_obj + c;
@@ -859,7 +807,7 @@ template <int N, bool NEAR>
 static hipError_t fwd_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
                              hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
-  const size_t sh = sizeof(float2) * (2 * N + L * Cfg<N>::LD);
+  const size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
   hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(N / L, bmax), dim3(kThreads), sh, s, p, d, slots, ns);
   return hipGetLastError();
 }
@@ -867,23 +815,30 @@ template <int N, bool NEAR>
 static hipError_t inv_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
                              const DebugPtrs& dbg, hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
-  const size_t sh = sizeof(float2) * (2 * N + L * Cfg<N>::LD);
+  const size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
   hipLaunchKernelGGL((k_inv_rows<N, NEAR>), dim3(N / L, bmax), dim3(kThreads), sh, s, p, d, slots, ns, dbg);
   return hipGetLastError();
 }
 template <int N, bool NEAR>
 static hipError_t fwd_cols_t(const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s) {
   constexpr int C = Cfg<N>::COLS;
-  const size_t sh = sizeof(float2) * (2 * N + C * Cfg<N>::LD);
+  const size_t sh = sizeof(float2) * (2 * N + Frame<N, C, true>::ELEMS);
   hipLaunchKernelGGL((k_fwd_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, ns);
   return hipGetLastError();
 }
 template <int N, bool NEAR>
-static hipError_t inv_cols_t(const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s) {
+static hipError_t inv_cols_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                             const DebugPtrs& dbg, hipStream_t s) {
   constexpr int C = Cfg<N>::COLS;
-  const size_t sh = sizeof(float2) * (2 * N + C * Cfg<N>::LD);
-  hipLaunchKernelGGL((k_inv_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, ns);
+  const size_t fft = sizeof(float2) * Frame<N, C, true>::ELEMS;
+  const size_t halo = sizeof(float) * (size_t)N * (C + 2 * p.ks_half);
+  const size_t sh = sizeof(float2) * 2 * N + (fft > halo ? fft : halo);
+  hipLaunchKernelGGL((k_inv_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, slots, ns, dbg);
   return hipGetLastError();
+}
+template <int N>
+static int cols_t() {
+  return Cfg<N>::COLS;
 }
 
 hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
@@ -911,34 +866,33 @@ hipError_t launch_fwd_cols(int n, bool near, const DevParams& p, const DevBufs& 
   PTY_DISPATCH_N(n, PTY_CASE)
 #undef PTY_CASE
 }
-hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax,
-                           hipStream_t s) {
-#define PTY_CASE(N) \
-  case N:           \
-    return near ? inv_cols_t<N, true>(p, d, ns, bmax, s) : inv_cols_t<N, false>(p, d, ns, bmax, s);
+hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
+                           int bmax, const DebugPtrs& dbg, hipStream_t s) {
+#define PTY_CASE(N)                                                  \
+  case N:                                                            \
+    return near ? inv_cols_t<N, true>(p, d, slots, ns, bmax, dbg, s) \
+                : inv_cols_t<N, false>(p, d, slots, ns, bmax, dbg, s);
   PTY_DISPATCH_N(n, PTY_CASE)
 #undef PTY_CASE
 }
 
-static int blur_tb(int n) { return (n % 32 == 0) ? 32 : (n % 16 == 0 ? 16 : 8); }
-int n_blur_tiles(int n) {
-  const int t = n / blur_tb(n);
-  return t * t;
+int n_err_slots(int n) {
+#define PTY_CASE(N) \
+  case N:           \
+    return N / cols_t<N>();
+  switch (n) {
+    PTY_CASE(8) PTY_CASE(16) PTY_CASE(24) PTY_CASE(32) PTY_CASE(48) PTY_CASE(64) PTY_CASE(96) PTY_CASE(128)
+    PTY_CASE(192) PTY_CASE(256) PTY_CASE(384) PTY_CASE(512) PTY_CASE(768) PTY_CASE(1024) default : return 0;
+  }
+#undef PTY_CASE
 }
 int n_obj_tiles(const DevParams& p) {
   return ((p.h_obj + kObjTile - 1) / kObjTile) * ((p.w_obj + kObjTile - 1) / kObjTile);
 }
 int n_probe_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
-int n_cc_chunks(int n) { return (n * n + kCcChunk - 1) / kCcChunk; }
 
-hipError_t launch_blur_factor(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                              hipStream_t s) {
-  const int tb = blur_tb(p.n);
-  hipLaunchKernelGGL(k_blur_factor, dim3(p.n / tb, p.n / tb, bmax), dim3(kThreads), 0, s, p, d, slots, ns, tb);
-  return hipGetLastError();
-}
 hipError_t launch_probe_accum(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
-  hipLaunchKernelGGL(k_probe_accum, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d, slots, ns);
+  hipLaunchKernelGGL(k_probe_accum, dim3(n_probe_blocks(p.n), p.k + 1), dim3(kThreads), 0, s, p, d, slots, ns);
   return hipGetLastError();
 }
 static dim3 obj_grid(const DevParams& p) {
@@ -948,9 +902,9 @@ hipError_t launch_obj_wmax(const DevParams& p, const DevBufs& d, const int* slot
   hipLaunchKernelGGL(k_obj_wmax, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns);
   return hipGetLastError();
 }
-hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns,
+hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool cc_sums,
                              const DebugPtrs& dbg, hipStream_t s) {
-  hipLaunchKernelGGL(k_obj_update, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, dbg);
+  hipLaunchKernelGGL(k_obj_update, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, cc_sums ? 1 : 0, dbg);
   return hipGetLastError();
 }
 hipError_t launch_probe_update(const DevParams& p, const DevBufs& d, hipStream_t s) {
@@ -962,15 +916,8 @@ hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
   return hipGetLastError();
 }
-hipError_t launch_cc_sums(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_cc_sums, dim3(n_cc_chunks(p.n), bmax), dim3(kThreads), 0, s, p, d, slots, ns);
-  return hipGetLastError();
-}
-hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                           hipStream_t s) {
-  (void)bmax;
-  hipLaunchKernelGGL(k_cc_apply, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, n_cc_chunks(p.n));
+hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
+  hipLaunchKernelGGL(k_cc_apply, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns);
   return hipGetLastError();
 }
 hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s) {

@@ -10,8 +10,6 @@ constexpr int kMaxHalf = 15;     // kernel_size <= 31
 constexpr int kMaxModes = 16;
 constexpr int kMaxBatch = 256;
 constexpr int kObjTile = 32;     // object tile side for the gather/update kernels
-constexpr int kBlurTile = 32;
-constexpr int kCcChunk = 4096;   // box pixels per constraint-sum block
 constexpr int kGramBlocks = 16;  // pixel chunks of the Gram matrix reduction
 
 struct DevParams {
@@ -35,15 +33,14 @@ struct DevBufs {
   const float2* tw;   // [N] exp(-2 pi i m / N)
   const float2* hnear;// [N] near-field 1D transfer function, exp(-i pi u~^2/(N^2 F_px))
   float2* X;          // [B][K][N][N] batch work frames
-  float* q;           // [B][N][N] incoherent mode sum of |Psi|^2
-  float* fac;         // [B][N][N] modulus factor
+  float* q;           // [B][N][N] vertically blurred sqrt(sum_k |Psi_k|^2) (or of the intensity)
   float2* dO;         // [B][N][N] per-slot object numerator sum_k conj(P_k) dpsi_k
   float2* nP;         // [K][N][N] probe numerator
   float* V;           // [N][N] probe weight sum_b |o_b|^2
   float* maxv_part;   // per-block max of V
   float* maxw_part;   // per-object-tile max of W
-  double* err_part;   // [n_pos][blur tiles per frame] data-error partial sums
-  double2* cc_part;   // [B][chunks] (sum |ln A|, sum |phi|)
+  double* err_part;   // [n_pos][column blocks per frame] data-error partial sums
+  double2* cc_part;   // [object tiles] (sum |ln A|, sum |phi|) weighted by box multiplicity
   double2* gram_part; // [pairs][kGramBlocks]
   float2* vmix;       // [K][K] eigenvectors (column j = mode j), float
   double* eig;        // [K] eigenvalues
@@ -53,13 +50,13 @@ struct DebugPtrs {
   float2* psi_new;  // [B][K][N][N] or null
   float2* n_obj;    // [H][W] or null
   float* w_obj;     // [H][W] or null
+  float* factor;    // [B][N][N] or null
 };
 
 // Kernel classes (for timing).
 enum KernelClass {
-  KC_FWD_ROWS = 0, KC_FWD_COLS, KC_BLUR, KC_INV_COLS, KC_INV_ROWS, KC_PROBE_ACC, KC_OBJ_WMAX,
-  KC_OBJ_UPDATE, KC_PROBE_UPDATE, KC_CC_SUMS, KC_CC_APPLY, KC_GRAM, KC_EIG, KC_REMIX, KC_ERR,
-  KC_COUNT
+  KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_PROBE_ACC, KC_OBJ_WMAX, KC_OBJ_UPDATE,
+  KC_PROBE_UPDATE, KC_CC_APPLY, KC_GRAM, KC_EIG, KC_REMIX, KC_ERR, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -67,18 +64,16 @@ extern const char* const kKernelNames[KC_COUNT];
 hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
                            int bmax, hipStream_t s);
 hipError_t launch_fwd_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s);
-hipError_t launch_blur_factor(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                              hipStream_t s);
-hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s);
+hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+                           const DebugPtrs& dbg, hipStream_t s);
 hipError_t launch_inv_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
                            int bmax, const DebugPtrs& dbg, hipStream_t s);
 hipError_t launch_probe_accum(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s);
 hipError_t launch_obj_wmax(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s);
-hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns,
+hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool cc_sums,
                              const DebugPtrs& dbg, hipStream_t s);
 hipError_t launch_probe_update(const DevParams& p, const DevBufs& d, hipStream_t s);
-hipError_t launch_cc_sums(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax, hipStream_t s);
-hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax, hipStream_t s);
+hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s);
 hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s);
 hipError_t launch_eig(const DevParams& p, const DevBufs& d, hipStream_t s);
 hipError_t launch_remix(const DevParams& p, const DevBufs& d, hipStream_t s);
@@ -91,9 +86,8 @@ hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* sl
                              hipStream_t s);
 
 int n_obj_tiles(const DevParams& p);
-int n_blur_tiles(int n);
+int n_err_slots(int n);  // data-error partials per position (one per column block)
 int n_probe_blocks(int n);
-int n_cc_chunks(int n);
 bool supported_n(int n);
 
 }  // namespace pty

@@ -184,20 +184,17 @@ ptycho_status run_batch(ptycho_ctx* c, const int* d_slots, int ns, int t, const 
   const bool near = c->prm.geometry == PTYCHO_NEAR_FIELD;
   hipStream_t s = c->stream;
   const int bm = ns;  // grid sized to the batch
+  const bool cc = in_window(c->prm, t);
   LAUNCH(c, KC_FWD_ROWS, launch_fwd_rows(p.n, near, p, d, d_slots, ns, bm, s));
   LAUNCH(c, KC_FWD_COLS, launch_fwd_cols(p.n, near, p, d, ns, bm, s));
-  LAUNCH(c, KC_BLUR, launch_blur_factor(p, d, d_slots, ns, bm, s));
-  LAUNCH(c, KC_INV_COLS, launch_inv_cols(p.n, near, p, d, ns, bm, s));
+  LAUNCH(c, KC_INV_COLS, launch_inv_cols(p.n, near, p, d, d_slots, ns, bm, dbg, s));
   LAUNCH(c, KC_INV_ROWS, launch_inv_rows(p.n, near, p, d, d_slots, ns, bm, dbg, s));
   const bool probe = t >= c->prm.probe_update_start;
   if (probe) LAUNCH(c, KC_PROBE_ACC, launch_probe_accum(p, d, d_slots, ns, s));
   LAUNCH(c, KC_OBJ_WMAX, launch_obj_wmax(p, d, d_slots, ns, s));
-  LAUNCH(c, KC_OBJ_UPDATE, launch_obj_update(p, d, d_slots, ns, dbg, s));
+  LAUNCH(c, KC_OBJ_UPDATE, launch_obj_update(p, d, d_slots, ns, cc, dbg, s));
   if (probe) LAUNCH(c, KC_PROBE_UPDATE, launch_probe_update(p, d, s));
-  if (in_window(c->prm, t)) {
-    LAUNCH(c, KC_CC_SUMS, launch_cc_sums(p, d, d_slots, ns, bm, s));
-    LAUNCH(c, KC_CC_APPLY, launch_cc_apply(p, d, d_slots, ns, bm, s));
-  }
+  if (cc) LAUNCH(c, KC_CC_APPLY, launch_cc_apply(p, d, d_slots, ns, s));
   return PTYCHO_OK;
 }
 
@@ -403,21 +400,21 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   c->bmax = B;
   DevBufs& d = c->db;
   float2 *obj, *probe, *tw, *hn, *X, *dO, *nP, *vmix;
-  float *pw, *amp, *q, *fac, *V, *maxv, *maxw;
+  float *pw, *amp, *q, *V, *maxv, *maxw;
   int2* pos;
   double *errp, *eig;
   double2 *ccp, *gramp;
   const int nobjt = n_obj_tiles(dp);
-  const int nbt = n_blur_tiles(n);
+  const int nbt = n_err_slots(n);
   ptycho_status st = PTYCHO_OK;
   if ((st = dev_alloc(c, &obj, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &probe, K * nn)) ||
       (st = dev_alloc(c, &pw, nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
       (st = dev_alloc(c, &pos, (size_t)p.n_pos)) || (st = dev_alloc(c, &tw, (size_t)n)) ||
       (st = dev_alloc(c, &hn, (size_t)n)) || (st = dev_alloc(c, &X, (size_t)B * K * nn)) ||
-      (st = dev_alloc(c, &q, (size_t)B * nn)) || (st = dev_alloc(c, &fac, (size_t)B * nn)) ||
+      (st = dev_alloc(c, &q, (size_t)B * nn)) ||
       (st = dev_alloc(c, &dO, (size_t)B * nn)) || (st = dev_alloc(c, &nP, K * nn)) || (st = dev_alloc(c, &V, nn)) ||
       (st = dev_alloc(c, &maxv, (size_t)n_probe_blocks(n))) || (st = dev_alloc(c, &maxw, (size_t)nobjt)) ||
-      (st = dev_alloc(c, &errp, (size_t)p.n_pos * nbt)) || (st = dev_alloc(c, &ccp, (size_t)B * n_cc_chunks(n))) ||
+      (st = dev_alloc(c, &errp, (size_t)p.n_pos * nbt)) || (st = dev_alloc(c, &ccp, (size_t)nobjt)) ||
       (st = dev_alloc(c, &gramp, (size_t)(K * (K + 1) / 2) * kGramBlocks)) || (st = dev_alloc(c, &vmix, (size_t)K * K)) ||
       (st = dev_alloc(c, &eig, (size_t)K)))
     return bail(st);
@@ -430,7 +427,6 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   d.hnear = hn;
   d.X = X;
   d.q = q;
-  d.fac = fac;
   d.dO = dO;
   d.nP = nP;
   d.V = V;
@@ -470,7 +466,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   INIT_TRY(hipMemcpyAsync(obj, object0, (size_t)p.obj_h * p.obj_w * sizeof(float2), kind_in(mem_kind), s));
   INIT_TRY(hipMemcpyAsync(probe, probe0, K * nn * sizeof(float2), kind_in(mem_kind), s));
   INIT_TRY(hipMemsetAsync(errp, 0, (size_t)p.n_pos * nbt * sizeof(double), s));
-  // measured amplitudes: copy raw intensities into the fac/q scratch when large enough? use a temporary.
+  // measured amplitudes: raw intensities staged in a temporary device buffer
   float* raw = nullptr;
   if (mem_kind == PTYCHO_MEM_HOST) {
     st = dev_alloc(c, &raw, (size_t)p.n_pos * nn);
@@ -543,7 +539,7 @@ ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order
   HIP_TRY(c, hipMemcpyAsync(c->d_order, c->h_order, (size_t)n_iter * np * sizeof(int32_t), hipMemcpyHostToDevice,
                             c->stream));
   const int B = c->prm.batch;
-  DebugPtrs none{nullptr, nullptr, nullptr};
+  DebugPtrs none{nullptr, nullptr, nullptr, nullptr};
   for (int it = 0; it < n_iter; ++it) {
     const int t = c->t + 1 + it;
     const int* ord = c->d_order + (size_t)it * np;
@@ -657,7 +653,12 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
       return fail(c, PTYCHO_E_HIP, std::string("exit waves: ") + hipGetErrorString(e));
     }
   }
-  DebugPtrs dbg{d_psin, d_nobj, d_wobj};
+  float* d_fac = nullptr;
+  if (factor && !alloc_tmp((size_t)B * nn * sizeof(float), (void**)&d_fac)) {
+    cleanup();
+    return fail(c, PTYCHO_E_OOM, "debug staging allocation failed");
+  }
+  DebugPtrs dbg{d_psin, d_nobj, d_wobj, d_fac};
   st = run_batch(c, c->d_order, B, t, dbg);
   auto copy = [&](float* dst, const void* src, size_t bytes) -> hipError_t {
     return dst ? hipMemcpyAsync(dst, src, bytes, kind_out(mem_kind), c->stream) : hipSuccess;
@@ -666,7 +667,7 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   if (st == PTYCHO_OK) {
     if (e == hipSuccess) e = copy(psi, d_psi, (size_t)B * K * nn * sizeof(float2));
     if (e == hipSuccess) e = copy(psi_new, d_psin, (size_t)B * K * nn * sizeof(float2));
-    if (e == hipSuccess) e = copy(factor, c->db.fac, (size_t)B * nn * sizeof(float));
+    if (e == hipSuccess) e = copy(factor, d_fac, (size_t)B * nn * sizeof(float));
     if (e == hipSuccess) e = copy(n_obj, d_nobj, no * sizeof(float2));
     if (e == hipSuccess) e = copy(w_obj, d_wobj, no * sizeof(float));
     if (e == hipSuccess) e = copy(n_probe, c->db.nP, K * nn * sizeof(float2));
