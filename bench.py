@@ -37,11 +37,11 @@ def per_slot_bytes(name, n, k):
     float = 4 B).  Probe reads are shared by the batch and left out."""
     nn = n * n
     return {
-        "fwd_rows": 8 * nn + 8 * k * nn,             # box gather in, K row-transformed frames out
+        "fwd_rows": 16 * nn + 8 * k * nn,            # box gather in (exit waves and V), K frames out
         "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, vertically blurred amplitude out
         "inv_cols": 16 * k * nn + 8 * nn,            # K frames in and out, blurred amplitude + measurement in
         "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
-        "probe_accum": 8 * k * nn + 8 * nn,          # K probe contributions in, box in
+        "probe_update_constraint": 8 * k * nn,       # K probe contributions in
     }.get(name)
 
 
@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 256 MiB device-to-device tensor copy (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -103,6 +106,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     spec, s, gen_s = build_workload()
     print(f"[bench] workload generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
     n, k, n_pos = s["n"], s["k"], len(s["positions"])

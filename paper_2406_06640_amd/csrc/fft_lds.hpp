@@ -17,19 +17,19 @@
 
 namespace pty {
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+__host__ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
-__device__ __forceinline__ float2 conjc(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float2 conjc(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
-__device__ __forceinline__ float2 mul_mi(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_mi(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
@@ -38,7 +38,7 @@ struct Dft;
 
 template <bool INV>
 struct Dft<2, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -47,7 +47,7 @@ struct Dft<2, INV> {
 
 template <bool INV>
 struct Dft<3, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     // X1 = v0 - (v1+v2)/2 -+ i (sqrt3/2)(v1-v2),  X2 = v0 - (v1+v2)/2 +- i (sqrt3/2)(v1-v2)
     const float s3 = 0.86602540378443864676f;
     float2 t1 = cadd(v[1], v[2]);
@@ -62,7 +62,7 @@ struct Dft<3, INV> {
 
 template <bool INV>
 struct Dft<4, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     float2 t0 = cadd(v[0], v[2]);
     float2 t1 = csub(v[0], v[2]);
     float2 t2 = cadd(v[1], v[3]);
@@ -76,7 +76,7 @@ struct Dft<4, INV> {
 
 template <bool INV>
 struct Dft<8, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     // split into even/odd radix-4 DFTs, then combine with w8^k
     float2 e[4] = {v[0], v[2], v[4], v[6]};
     float2 o[4] = {v[1], v[3], v[5], v[7]};
@@ -97,6 +97,42 @@ struct Dft<8, INV> {
     v[6] = csub(e[2], o2);
     v[3] = cadd(e[3], o3);
     v[7] = csub(e[3], o3);
+  }
+};
+
+template <bool INV>
+struct Dft<16, INV> {
+  // 16 = 4 x 4: radix-4 DFTs over n1 for each n2, internal twiddles w16^(n2 k1),
+  // radix-4 DFTs over n2 for each k1; output index k1 + 4 k2.
+  __host__ __device__ __forceinline__ static float2 w16(float2 a, int m) {
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+    const float sg = INV ? 1.0f : -1.0f;  // exp(sg * 2 pi i m / 16)
+    switch (m) {
+      case 1: return cmul(a, make_float2(c1, sg * s1));
+      case 2: return make_float2(h * (a.x - sg * a.y), h * (a.y + sg * a.x));
+      case 3: return cmul(a, make_float2(s1, sg * c1));
+      case 4: return mul_mi<INV>(a);
+      case 6: return make_float2(-h * (a.x + sg * a.y), h * (sg * a.x - a.y));
+      case 9: return cmul(a, make_float2(-c1, -sg * s1));
+      default: return a;
+    }
+  }
+  __host__ __device__ __forceinline__ static void run(float2* v) {
+    float2 y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = (n2 && k1) ? w16(t[k1], n2 * k1) : t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
   }
 };
 
@@ -174,24 +210,30 @@ __device__ __forceinline__ void fft_lines(float2* buf, int ld, const float2* tw)
 }
 
 // ---------------------------------------------------------------------------
-// Register-fed transforms: the first stage reads its inputs through a Load
-// functor (global memory, with any elementwise prologue fused) and the last
-// stage hands its outputs to a Store functor, so only the middle stages use
-// LDS.  Lines are laid out in LDS by Frame<N, NL, LF>:
-//   LF = false: line-major   (a row pass: thread butterflies run along a line)
+// Register-fed transforms: the first stage takes its inputs from registers
+// that a Load functor filled (global memory, with any elementwise prologue
+// fused) and the last stage hands its outputs to a Store functor, so only the
+// middle exchanges use LDS.  Lines are laid out in LDS by Frame<N, NL, LF>:
+//   LF = false: line-major (a row pass: a thread's butterflies run along a
+//               line); every 16th position is followed by a pad slot so the
+//               stride-R writes of the first stage spread over the banks
 //   LF = true : position-major (a column pass: consecutive threads take
 //               consecutive lines, i.e. adjacent columns of the frame, so
 //               global accesses are coalesced row segments)
 // Load(slot, line, pos) -> float2 and Store(slot, line, pos, float2) receive a
 // per-thread slot index (butterfly i, leg r) that is the same for every call
 // of the same transform shape, so callers can keep per-element registers.
+// The gather of the next transform's inputs can be issued (fft_gather) while
+// the current one is still in its LDS stages (fft_first / fft_rest).
 // ---------------------------------------------------------------------------
 
 template <int N, int NL, bool LF>
 struct Frame {
-  static constexpr int LD = LF ? NL + 1 : N + 1;
+  static constexpr int LD = LF ? NL + 1 : N + (N >> 4) + 1;
   static constexpr int ELEMS = LF ? N * LD : NL * LD;
-  __device__ __forceinline__ static int lidx(int line, int pos) { return LF ? pos * LD + line : line * LD + pos; }
+  __device__ __forceinline__ static int lidx(int line, int pos) {
+    return LF ? pos * LD + line : line * LD + pos + (pos >> 4);
+  }
   template <int M>
   __device__ __forceinline__ static void map(int f, int& line, int& j) {
     if (LF) {
@@ -202,11 +244,6 @@ struct Frame {
       j = f - line * M;
     }
   }
-};
-
-template <int N, int R>
-struct StageShape {
-  static constexpr int M = N / R;
 };
 
 template <int N, int NL, int R>
@@ -284,7 +321,7 @@ __device__ __forceinline__ void last_stage(float2* buf, const float2* __restrict
       F::template map<M>(f, line, j);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float2 w = tw[r * j * (N / (NS * R))];
+        const float2 w = tw[r * j];
         v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
       }
       Dft<R, INV>::run(v[i]);
@@ -304,78 +341,57 @@ __device__ __forceinline__ void stages_from_lds(float2* buf, const float2* tw, S
   }
 }
 
-// First stage (radix R0) fed by Load, remaining stages through LDS, last to Store.
-// LOAD_LDS: the loads read `buf`, so they all finish before stage 0 writes it.
-// On return the last stage's LDS reads are done but no barrier follows; a
-// caller that rewrites `buf` afterwards must synchronise first.
-template <int N, int NL, bool LF, bool INV, bool LOAD_LDS, bool STORE_LDS, class Load, class Store, int R0,
-          int... Rs>
-__device__ __forceinline__ void fft_reg_impl(float2* buf, const float2* __restrict__ tw, Load& load, Store& store) {
-  using F = Frame<N, NL, LF>;
-  constexpr int M = N / R0;
-  constexpr int TOT = NL * M;
-  constexpr int NB = (TOT + 255) / 256;
-  float2 v[NB][R0];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
-    if (TOT % 256 == 0 || f < TOT) {
-      int line, j;
-      F::template map<M>(f, line, j);
-#pragma unroll
-      for (int r = 0; r < R0; ++r) v[i][r] = load(i * R0 + r, line, j + r * M);
-    }
-  }
-  if constexpr (sizeof...(Rs) == 0) {
-    if (LOAD_LDS && STORE_LDS) __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int f = threadIdx.x + i * 256;
-      if (TOT % 256 == 0 || f < TOT) {
-        int line, j;
-        F::template map<M>(f, line, j);
-        Dft<R0, INV>::run(v[i]);
-#pragma unroll
-        for (int r = 0; r < R0; ++r) store(i * R0 + r, line, j + r * M, v[i][r]);
-      }
-    }
-  } else {
-    if (LOAD_LDS) __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int f = threadIdx.x + i * 256;
-      if (TOT % 256 == 0 || f < TOT) {
-        int line, j;
-        F::template map<M>(f, line, j);
-        Dft<R0, INV>::run(v[i]);
-#pragma unroll
-        for (int r = 0; r < R0; ++r) buf[F::lidx(line, j * R0 + r)] = v[i][r];
-      }
-    }
-    __syncthreads();
-    stages_from_lds<N, NL, LF, INV, STORE_LDS, Store, R0, Rs...>(buf, tw, store);
-  }
-}
+template <int... Rs>
+struct Radices;
+template <int R0, int... Rest>
+struct Radices<R0, Rest...> {
+  static constexpr int FIRST = R0;
+  static constexpr int LAST = sizeof...(Rest) ? Radices<Rest...>::LAST : R0;
+  static constexpr int COUNT = 1 + sizeof...(Rest);
+};
+template <int R0>
+struct Radices<R0> {
+  static constexpr int FIRST = R0;
+  static constexpr int LAST = R0;
+  static constexpr int COUNT = 1;
+};
 
-// Radix plans (first radix, then the rest); the first and last radices set
-// the Load and Store slot shapes: FirstR<N>, LastR<N>.
-template <int N> struct Plan;
-template <> struct Plan<8> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<8, NL, LF, INV, LL, SL, L, S, 8>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 8; };
-template <> struct Plan<16> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<16, NL, LF, INV, LL, SL, L, S, 4, 4>(b, t, l, s); } static constexpr int FIRST = 4, LAST = 4; };
-template <> struct Plan<24> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<24, NL, LF, INV, LL, SL, L, S, 3, 8>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 8; };
-template <> struct Plan<32> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<32, NL, LF, INV, LL, SL, L, S, 8, 4>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 4; };
-template <> struct Plan<48> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<48, NL, LF, INV, LL, SL, L, S, 3, 4, 4>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 4; };
-template <> struct Plan<64> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<64, NL, LF, INV, LL, SL, L, S, 8, 8>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 8; };
-template <> struct Plan<96> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<96, NL, LF, INV, LL, SL, L, S, 3, 8, 4>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 4; };
-template <> struct Plan<128> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<128, NL, LF, INV, LL, SL, L, S, 8, 4, 4>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 4; };
-template <> struct Plan<192> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<192, NL, LF, INV, LL, SL, L, S, 3, 8, 8>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 8; };
-template <> struct Plan<256> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<256, NL, LF, INV, LL, SL, L, S, 4, 4, 4, 4>(b, t, l, s); } static constexpr int FIRST = 4, LAST = 4; };
-template <> struct Plan<384> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<384, NL, LF, INV, LL, SL, L, S, 3, 8, 4, 4>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 4; };
-template <> struct Plan<512> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<512, NL, LF, INV, LL, SL, L, S, 8, 8, 8>(b, t, l, s); } static constexpr int FIRST = 8, LAST = 8; };
-template <> struct Plan<768> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<768, NL, LF, INV, LL, SL, L, S, 3, 4, 8, 8>(b, t, l, s); } static constexpr int FIRST = 3, LAST = 8; };
-template <> struct Plan<1024> { template <int NL, bool LF, bool INV, bool LL, bool SL, class L, class S> __device__ static void run(float2* b, const float2* t, L& l, S& s) { fft_reg_impl<1024, NL, LF, INV, LL, SL, L, S, 4, 4, 8, 8>(b, t, l, s); } static constexpr int FIRST = 4, LAST = 8; };
+// Radix plans: N = product of the radices (first radix applied first).
+template <int N> struct PlanOf;
+template <> struct PlanOf<8> { using R = Radices<8>; };
+template <> struct PlanOf<16> { using R = Radices<16>; };
+template <> struct PlanOf<24> { using R = Radices<3, 8>; };
+template <> struct PlanOf<32> { using R = Radices<8, 4>; };
+template <> struct PlanOf<48> { using R = Radices<3, 16>; };
+template <> struct PlanOf<64> { using R = Radices<8, 8>; };
+template <> struct PlanOf<96> { using R = Radices<3, 8, 4>; };
+template <> struct PlanOf<128> { using R = Radices<16, 8>; };
+template <> struct PlanOf<192> { using R = Radices<3, 8, 8>; };
+template <> struct PlanOf<256> { using R = Radices<16, 16>; };
+template <> struct PlanOf<384> { using R = Radices<3, 8, 16>; };
+template <> struct PlanOf<512> { using R = Radices<8, 8, 8>; };
+template <> struct PlanOf<768> { using R = Radices<3, 16, 16>; };
+template <> struct PlanOf<1024> { using R = Radices<16, 8, 8>; };
 
-// Enumerate this thread's Load (first-stage) or Store (last-stage) slots:
+template <class Rads>
+struct RestOf;
+template <int R0, int... Rest>
+struct RestOf<Radices<R0, Rest...>> {
+  template <int N, int NL, bool LF, bool INV, bool STORE_LDS, class Store>
+  __device__ __forceinline__ static void run(float2* buf, const float2* tw, Store& store) {
+    stages_from_lds<N, NL, LF, INV, STORE_LDS, Store, R0, Rest...>(buf, tw, store);
+  }
+};
+
+template <int N, int NL>
+struct RegShape {
+  using R = typename PlanOf<N>::R;
+  static constexpr bool SINGLE = R::COUNT == 1;
+  static constexpr int LOAD_SLOTS = Slots<N, NL, R::FIRST>::COUNT;
+  static constexpr int STORE_SLOTS = Slots<N, NL, R::LAST>::COUNT;
+};
+
+// Enumerate this thread's first-stage (Load) or last-stage (Store) slots:
 // fn(slot, line, pos) for every element the transform will hand it.
 template <int N, int NL, bool LF, int R, class Fn>
 __device__ __forceinline__ void for_slots(Fn&& fn) {
@@ -396,23 +412,67 @@ __device__ __forceinline__ void for_slots(Fn&& fn) {
 }
 template <int N, int NL, bool LF, class Fn>
 __device__ __forceinline__ void for_load_slots(Fn&& fn) {
-  for_slots<N, NL, LF, Plan<N>::FIRST>(fn);
+  for_slots<N, NL, LF, PlanOf<N>::R::FIRST>(fn);
 }
 template <int N, int NL, bool LF, class Fn>
 __device__ __forceinline__ void for_store_slots(Fn&& fn) {
-  for_slots<N, NL, LF, Plan<N>::LAST>(fn);
+  for_slots<N, NL, LF, PlanOf<N>::R::LAST>(fn);
 }
 
-// Register-fed transform of NL lines of length N.  Load and Store see slots
-// 0 .. LoadSlots-1 and 0 .. StoreSlots-1 respectively.
+// Gather the first-stage inputs: v[slot] = load(slot, line, pos).
+template <int N, int NL, bool LF, class Load>
+__device__ __forceinline__ void fft_gather(float2* v, Load& load) {
+  for_load_slots<N, NL, LF>([&](int s, int line, int pos) { v[s] = load(s, line, pos); });
+}
+
+// First stage from registers.  Multi-stage plans write the stage output to
+// LDS and synchronise; single-stage plans transform in registers only.
+// LOAD_LDS: the gathered values came from `buf`; all threads finish reading first.
+template <int N, int NL, bool LF, bool INV, bool LOAD_LDS = false>
+__device__ __forceinline__ void fft_first(float2* v, float2* buf) {
+  using F = Frame<N, NL, LF>;
+  constexpr int R0 = PlanOf<N>::R::FIRST;
+  constexpr int M = N / R0;
+  constexpr int TOT = NL * M;
+  constexpr int NB = (TOT + 255) / 256;
+  if (LOAD_LDS) __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int f = threadIdx.x + i * 256;
+    if (TOT % 256 == 0 || f < TOT) {
+      Dft<R0, INV>::run(v + i * R0);
+      if constexpr (!RegShape<N, NL>::SINGLE) {
+        int line, j;
+        F::template map<M>(f, line, j);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) buf[F::lidx(line, j * R0 + r)] = v[i * R0 + r];
+      }
+    }
+  }
+  if constexpr (!RegShape<N, NL>::SINGLE) __syncthreads();
+}
+
+// Remaining stages; the last hands its outputs to Store.  For a single-stage
+// plan this stores the registers transformed by fft_first.  On return the
+// last stage's LDS reads are done but no barrier follows: a caller that
+// rewrites `buf` afterwards must synchronise first.
+template <int N, int NL, bool LF, bool INV, bool STORE_LDS = false, class Store>
+__device__ __forceinline__ void fft_rest(const float2* v, float2* buf, const float2* tw, Store& store) {
+  if constexpr (RegShape<N, NL>::SINGLE) {
+    if (STORE_LDS) __syncthreads();
+    for_load_slots<N, NL, LF>([&](int s, int line, int pos) { store(s, line, pos, v[s]); });
+  } else {
+    RestOf<typename PlanOf<N>::R>::template run<N, NL, LF, INV, STORE_LDS>(buf, tw, store);
+  }
+}
+
+// Whole transform of NL lines: gather, first stage, remaining stages.
 template <int N, int NL, bool LF, bool INV, bool LOAD_LDS = false, bool STORE_LDS = false, class Load, class Store>
 __device__ __forceinline__ void fft_reg(float2* buf, const float2* tw, Load& load, Store& store) {
-  Plan<N>::template run<NL, LF, INV, LOAD_LDS, STORE_LDS>(buf, tw, load, store);
+  float2 v[RegShape<N, NL>::LOAD_SLOTS];
+  fft_gather<N, NL, LF>(v, load);
+  fft_first<N, NL, LF, INV, LOAD_LDS>(v, buf);
+  fft_rest<N, NL, LF, INV, STORE_LDS>(v, buf, tw, store);
 }
-template <int N, int NL>
-struct RegShape {
-  static constexpr int LOAD_SLOTS = Slots<N, NL, Plan<N>::FIRST>::COUNT;
-  static constexpr int STORE_SLOTS = Slots<N, NL, Plan<N>::LAST>::COUNT;
-};
 
 }  // namespace pty

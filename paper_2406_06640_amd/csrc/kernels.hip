@@ -9,11 +9,12 @@
 //              Psi' = factor Psi, inverse 1D transform along y
 //   inv_rows   inverse along x -> psi'; dpsi = psi' - o_b P_k; per-slot object
 //              numerator sum_k conj(P_k) dpsi_k; X <- conj(o_b) dpsi_k
-//   probe_acc  N_P,k = sum_b X[b][k] and V = sum_b |o_b|^2 in slot order
-//   obj_wmax / obj_update   W and N_O gathered per object tile in slot order; O update
-//                           (and, in constraint windows, the C-bar sums of Eq. 11)
-//   probe_update            P_k update; sum_k |P_k|^2 refreshed
-//   cc_apply                complex constraint, Eq. (9)-(10) (box 2)
+//   (fwd_rows side blocks: per-tile max of W = sum_b |P(r - r_b)|^2 and
+//              V = sum_b |o_b|^2, both from the pre-update state)
+//   obj_update N_O gathered per object tile in slot order; O update (and, in
+//              constraint windows, the C-bar sums of Eq. 11)
+//   post       N_P,k = sum_b X[b][k] in slot order, P_k update, sum_k |P_k|^2;
+//              complex constraint, Eq. (9)-(10) (box 2)
 // Near-field frames use the separable paraxial transfer function: each 1D
 // pass is forward FFT, multiply by h, inverse FFT.  Every reduction runs in a
 // fixed order (no atomics), so results are bitwise reproducible.
@@ -26,8 +27,8 @@
 namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
-    "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "probe_accum", "obj_wmax",
-    "obj_update", "probe_update", "cc_apply", "gram", "eig", "mode_remix", "err_reduce"};
+    "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_update", "probe_update_constraint",
+    "gram", "eig", "mode_remix", "err_reduce"};
 
 constexpr int kThreads = 256;
 
@@ -38,59 +39,96 @@ constexpr int largest_divisor_le(int n, int cap) {
   return best;
 }
 
-// Lines per block: ~2048 elements for row blocks, ~4096 for column blocks,
-// with the column block's LDS (lines + twiddle and transfer tables) <= 64 KiB.
+// Lines per block: ~4096 elements (16 per thread) for row and column blocks.
 template <int N>
 struct Cfg {
-  static constexpr int LD = N + 1;  // LDS line stride (float2), padded against bank conflicts
-  static constexpr int ROWS = largest_divisor_le(N, 2048 / N < 1 ? 1 : 2048 / N);
-  static constexpr int CCAP0 = (65536 / 8 - 2 * N) / LD;
-  static constexpr int CCAP1 = 4096 / N < 8 ? 8 : (4096 / N > 64 ? 64 : 4096 / N);
-  static constexpr int COLS = largest_divisor_le(N, CCAP0 < CCAP1 ? CCAP0 : CCAP1);
+  static constexpr int ROWS = largest_divisor_le(N, 4096 / N < 1 ? 1 : 4096 / N);
+  static constexpr int CCAP = 4096 / N < 4 ? 4 : (4096 / N > 64 ? 64 : 4096 / N);
+  static constexpr int COLS = largest_divisor_le(N, CCAP);
   static_assert(N % ROWS == 0 && N % COLS == 0, "tile must divide N");
 };
 
+// Block reductions in a fixed order: butterfly over the 64 lanes of each wave,
+// then the 4 wave results in order.  `sh` holds kThreads / 64 entries.
 __device__ __forceinline__ double block_sum_d(double v, double* sh) {
-  // fixed-order tree over the 256 threads of the block
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = sh[0];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  return r;
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 __device__ __forceinline__ float block_max_f(float v, float* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
-    __syncthreads();
-  }
-  float r = sh[0];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  return r;
+  return fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
 }
+
+__host__ __device__ __forceinline__ int n_probe_blocks_dev(int n) { return (n * n + kThreads - 1) / kThreads; }
 
 // ---------------------------------------------------------------------------
 // Row passes (lines along x; Frame<N, L, false>)
 // ---------------------------------------------------------------------------
 
+// One 1D pass over the K modes of a block's lines, with the next mode's inputs
+// gathered while the current mode is in its LDS stages.  gather(k, v) fills the
+// first-stage registers of mode k; store_for(k) returns the Store functor of mode
+// k.  NEAR: each pass is F^-1 h F (or F^-1 conj(h) F when CONJ), the transfer
+// function applied between the two transforms in LDS.
+template <int N, int NL, bool LF, bool INV, bool NEAR, bool CONJ, class Gather, class StoreFor>
+__device__ __forceinline__ void mode_loop(int K, float2* buf, const float2* tw, const float2* hn, Gather& gather,
+                                          StoreFor& store_for) {
+  using F = Frame<N, NL, LF>;
+  constexpr bool SINGLE = RegShape<N, NL>::SINGLE;
+  float2 v[RegShape<N, NL>::LOAD_SLOTS];
+  gather(0, v);
+  for (int k = 0; k < K; ++k) {
+    auto store = store_for(k);
+    if (!NEAR) {
+      fft_first<N, NL, LF, INV>(v, buf);
+      if (!SINGLE && k + 1 < K) gather(k + 1, v);
+      fft_rest<N, NL, LF, INV>(v, buf, tw, store);
+      if (SINGLE && k + 1 < K) gather(k + 1, v);
+    } else {
+      auto to_lds = [&](int s, int line, int pos, float2 x) {
+        buf[F::lidx(line, pos)] = CONJ ? cmulc(x, hn[pos]) : cmul(x, hn[pos]);
+      };
+      auto from_lds = [&](int s, int line, int pos) { return buf[F::lidx(line, pos)]; };
+      fft_first<N, NL, LF, false>(v, buf);
+      if (!SINGLE && k + 1 < K) gather(k + 1, v);
+      fft_rest<N, NL, LF, false, true>(v, buf, tw, to_lds);
+      if (SINGLE && k + 1 < K) gather(k + 1, v);
+      __syncthreads();
+      fft_reg<N, NL, LF, true, true, false>(buf, tw, from_lds, store);
+    }
+    __syncthreads();
+  }
+}
+
+struct SideScratch;
+__device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
+                         SideScratch& sc);
+
+// Blocks with blockIdx.y >= ns do the batch's side work (see side_job).
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns) {
+                                                       int ns, int with_v) {
   constexpr int L = Cfg<N>::ROWS;
-  using F = Frame<N, L, false>;
   constexpr int LS = RegShape<N, L>::LOAD_SLOTS;
   extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
   const int b = blockIdx.y;
-  if (b >= ns) return;
+  if (b >= ns) {
+    side_job(p, d, slots, ns, (b - ns) * gridDim.x + blockIdx.x, with_v != 0,
+             *reinterpret_cast<SideScratch*>(sm));
+    return;
+  }
   const int y0 = blockIdx.x * L;
   const int2 rc = d.pos[slots[b]];
   for (int i = threadIdx.x; i < N; i += kThreads) {
@@ -98,33 +136,27 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, c
     if (NEAR) hn[i] = d.hnear[i];
   }
   float2 o[LS];
-  for_load_slots<N, L, false>([&](int s, int line, int pos) {
-    o[s] = d.obj[(size_t)(rc.x + y0 + line) * p.w_obj + rc.y + pos];
-  });
+  const float2* orow = d.obj + (size_t)(rc.x + y0) * p.w_obj + rc.y;
+  for_load_slots<N, L, false>([&](int s, int line, int pos) { o[s] = orow[line * p.w_obj + pos]; });
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  for (int k = 0; k < p.k; ++k) {
-    const float2* pk = d.probe + (size_t)k * N * N + (size_t)y0 * N;
-    float2* out = d.X + ((size_t)(b * p.k + k) * N + y0) * N;
+  const float2* p0 = d.probe + (size_t)y0 * N;
+  float2* x0 = d.X + ((size_t)b * p.k * N + y0) * N;
+  auto gather = [&](int k, float2* v) {
+    const float2* pk = p0 + (size_t)k * N * N;
     auto load = [&](int s, int line, int pos) { return cmul(o[s], pk[line * N + pos]); };
-    auto store = [&](int s, int line, int pos, float2 v) { out[line * N + pos] = cscale(v, scale); };
-    if (!NEAR) {
-      fft_reg<N, L, false, false>(buf, tw, load, store);
-    } else {
-      auto to_lds = [&](int s, int line, int pos, float2 v) { buf[F::lidx(line, pos)] = cmul(v, hn[pos]); };
-      auto from_lds = [&](int s, int line, int pos) { return buf[F::lidx(line, pos)]; };
-      fft_reg<N, L, false, false, false, true>(buf, tw, load, to_lds);
-      __syncthreads();
-      fft_reg<N, L, false, true, true, false>(buf, tw, from_lds, store);
-    }
-    __syncthreads();
-  }
+    fft_gather<N, L, false>(v, load);
+  };
+  auto store_for = [&](int k) {
+    float2* out = x0 + (size_t)k * N * N;
+    return [=](int s, int line, int pos, float2 v) { out[line * N + pos] = cscale(v, scale); };
+  };
+  mode_loop<N, L, false, false, NEAR, false>(p.k, buf, tw, hn, gather, store_for);
 }
 
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                        int ns, DebugPtrs dbg) {
   constexpr int L = Cfg<N>::ROWS;
-  using F = Frame<N, L, false>;
   constexpr int SS = RegShape<N, L>::STORE_SLOTS;
   extern __shared__ float2 sm[];
   float2* tw = sm;
@@ -138,36 +170,36 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, c
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
-  float2 o[SS], acc[SS];
-  for_store_slots<N, L, false>([&](int s, int line, int pos) {
-    o[s] = d.obj[(size_t)(rc.x + y0 + line) * p.w_obj + rc.y + pos];
-    acc[s] = make_float2(0.f, 0.f);
-  });
+  // the box rows are re-read in every mode's epilogue (cache hits) rather than
+  // held in registers, which keeps the occupancy of this pass up
+  float2 acc[SS];
+  const float2* orow = d.obj + (size_t)(rc.x + y0) * p.w_obj + rc.y;
+#pragma unroll
+  for (int i = 0; i < SS; ++i) acc[i] = make_float2(0.f, 0.f);
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  for (int k = 0; k < p.k; ++k) {
-    float2* fr = d.X + ((size_t)(b * p.k + k) * N + y0) * N;
-    const float2* pk = d.probe + (size_t)k * N * N + (size_t)y0 * N;
-    float2* dbgp = dbg.psi_new ? dbg.psi_new + ((size_t)(b * p.k + k) * N + y0) * N : nullptr;
+  float2* x0 = d.X + ((size_t)b * p.k * N + y0) * N;
+  const float2* p0 = d.probe + (size_t)y0 * N;
+  float2* dbg0 = dbg.psi_new ? dbg.psi_new + ((size_t)b * p.k * N + y0) * N : nullptr;
+  auto gather = [&](int k, float2* v) {
+    const float2* fr = x0 + (size_t)k * N * N;
     auto load = [&](int s, int line, int pos) { return fr[line * N + pos]; };
-    auto store = [&](int s, int line, int pos, float2 v) {
+    fft_gather<N, L, false>(v, load);
+  };
+  auto store_for = [&](int k) {
+    float2* fr = x0 + (size_t)k * N * N;
+    const float2* pk = p0 + (size_t)k * N * N;
+    float2* dbgp = dbg0 ? dbg0 + (size_t)k * N * N : nullptr;
+    return [&, fr, pk, dbgp](int s, int line, int pos, float2 v) {
       const float2 psi_new = cscale(v, scale);
       const float2 pv = pk[line * N + pos];
-      const float2 dpsi = csub(psi_new, cmul(o[s], pv));
+      const float2 o = orow[line * p.w_obj + pos];
+      const float2 dpsi = csub(psi_new, cmul(o, pv));
       acc[s] = cadd(acc[s], cmulc(dpsi, pv));  // conj(P) dpsi
-      fr[line * N + pos] = cmulc(dpsi, o[s]);    // conj(o) dpsi
+      fr[line * N + pos] = cmulc(dpsi, o);       // conj(o) dpsi
       if (dbgp) dbgp[line * N + pos] = psi_new;
     };
-    if (!NEAR) {
-      fft_reg<N, L, false, true>(buf, tw, load, store);
-    } else {
-      auto to_lds = [&](int s, int line, int pos, float2 v) { buf[F::lidx(line, pos)] = cmulc(v, hn[pos]); };
-      auto from_lds = [&](int s, int line, int pos) { return buf[F::lidx(line, pos)]; };
-      fft_reg<N, L, false, false, false, true>(buf, tw, load, to_lds);
-      __syncthreads();
-      fft_reg<N, L, false, true, true, false>(buf, tw, from_lds, store);
-    }
-    __syncthreads();
-  }
+  };
+  mode_loop<N, L, false, true, NEAR, true>(p.k, buf, tw, hn, gather, store_for);
   float2* dO = d.dO + ((size_t)b * N + y0) * N;
   for_store_slots<N, L, false>([&](int s, int line, int pos) { dO[line * N + pos] = acc[s]; });
 }
@@ -188,7 +220,6 @@ __device__ __forceinline__ int wrap(int t, int n) {
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, int ns) {
   constexpr int C = Cfg<N>::COLS;
-  using F = Frame<N, C, true>;
   constexpr int SS = RegShape<N, C>::STORE_SLOTS;
   extern __shared__ float2 sm[];
   float2* tw = sm;
@@ -205,25 +236,21 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, i
 #pragma unroll
   for (int i = 0; i < SS; ++i) acc[i] = 0.f;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  for (int k = 0; k < p.k; ++k) {
-    float2* fr = d.X + (size_t)(b * p.k + k) * N * N + x0;
-    auto load = [&](int s, int c, int y) { return fr[(size_t)y * N + c]; };
-    auto store = [&](int s, int c, int y, float2 v) {
+  float2* f0 = d.X + (size_t)b * p.k * N * N + x0;
+  auto gather = [&](int k, float2* v) {
+    const float2* fr = f0 + (size_t)k * N * N;
+    auto load = [&](int s, int c, int y) { return fr[y * N + c]; };
+    fft_gather<N, C, true>(v, load);
+  };
+  auto store_for = [&](int k) {
+    float2* fr = f0 + (size_t)k * N * N;
+    return [&, fr](int s, int c, int y, float2 v) {
       v = cscale(v, scale);
-      fr[(size_t)y * N + c] = v;
+      fr[y * N + c] = v;
       acc[s] += v.x * v.x + v.y * v.y;
     };
-    if (!NEAR) {
-      fft_reg<N, C, true, false>(buf, tw, load, store);
-    } else {
-      auto to_lds = [&](int s, int c, int y, float2 v) { buf[F::lidx(c, y)] = cmul(v, hn[y]); };
-      auto from_lds = [&](int s, int c, int y) { return buf[F::lidx(c, y)]; };
-      fft_reg<N, C, true, false, false, true>(buf, tw, load, to_lds);
-      __syncthreads();
-      fft_reg<N, C, true, true, true, false>(buf, tw, from_lds, store);
-    }
-    __syncthreads();
-  }
+  };
+  mode_loop<N, C, true, false, NEAR, false>(p.k, buf, tw, hn, gather, store_for);
   // vertical blur of the modelled amplitude (or intensity) over whole columns
   float* tile = reinterpret_cast<float*>(buf);
   constexpr int TS = C + 1;
@@ -236,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, i
   for_store_slots<N, C, true>([&](int s, int c, int y) {
     float g = p.gy[0] * tile[y * TS + c];
     for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
-    q[(size_t)y * N + c] = g;
+    q[y * N + c] = g;
   });
 }
 
@@ -246,7 +273,6 @@ template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                        int ns, DebugPtrs dbg) {
   constexpr int C = Cfg<N>::COLS;
-  using F = Frame<N, C, true>;
   constexpr int LS = RegShape<N, C>::LOAD_SLOTS;
   extern __shared__ float2 sm[];
   __shared__ double red[kThreads];
@@ -265,10 +291,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, c
   const int TW = C + 2 * h;
   float* tile = reinterpret_cast<float*>(buf);
   const float* q = d.q + (size_t)b * N * N;
-  for (int e = threadIdx.x; e < N * TW; e += kThreads) {
-    const int y = e / TW, cc = e - y * TW;
-    tile[e] = q[(size_t)y * N + wrap(x0 - h + cc, N)];
-  }
+  for (int y = threadIdx.x >> 5; y < N; y += kThreads >> 5)
+    for (int cc = threadIdx.x & 31; cc < TW; cc += 32) tile[y * TW + cc] = q[y * N + wrap(x0 - h + cc, N)];
   __syncthreads();
   float f[LS];
   double err = 0.0;
@@ -278,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, c
     const float* row = tile + y * TW + c + h;
     float g = p.gx[0] * row[0];
     for (int dx = 1; dx <= h; ++dx) g += p.gx[dx] * (row[-dx] + row[dx]);
-    const float a = amp[(size_t)y * N + c];
+    const float a = amp[y * N + c];
     float ag;
     if (p.blur_intensity) {
       ag = sqrtf(g);
@@ -287,85 +311,29 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, c
       ag = g;
       f[s] = a / (g + p.eps);
     }
-    if (dbgf) dbgf[(size_t)y * N + c] = f[s];
+    if (dbgf) dbgf[y * N + c] = f[s];
     const double dd = (double)a - (double)ag;
     err += dd * dd;
   });
   const double tot = block_sum_d(err, red);  // also orders the tile reads before the FFT's LDS writes
   if (threadIdx.x == 0) d.err_part[(size_t)pat * (N / C) + blockIdx.x] = tot;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  for (int k = 0; k < p.k; ++k) {
-    float2* fr = d.X + (size_t)(b * p.k + k) * N * N + x0;
-    auto load = [&](int s, int c, int y) { return cscale(fr[(size_t)y * N + c], f[s]); };
-    auto store = [&](int s, int c, int y, float2 v) { fr[(size_t)y * N + c] = cscale(v, scale); };
-    if (!NEAR) {
-      fft_reg<N, C, true, true>(buf, tw, load, store);
-    } else {
-      auto to_lds = [&](int s, int c, int y, float2 v) { buf[F::lidx(c, y)] = cmulc(v, hn[y]); };
-      auto from_lds = [&](int s, int c, int y) { return buf[F::lidx(c, y)]; };
-      fft_reg<N, C, true, false, false, true>(buf, tw, load, to_lds);
-      __syncthreads();
-      fft_reg<N, C, true, true, true, false>(buf, tw, from_lds, store);
-    }
-    __syncthreads();
-  }
+  float2* f0 = d.X + (size_t)b * p.k * N * N + x0;
+  auto gather = [&](int k, float2* v) {
+    const float2* fr = f0 + (size_t)k * N * N;
+    auto load = [&](int s, int c, int y) { return cscale(fr[y * N + c], f[s]); };
+    fft_gather<N, C, true>(v, load);
+  };
+  auto store_for = [&](int k) {
+    float2* fr = f0 + (size_t)k * N * N;
+    return [=](int s, int c, int y, float2 v) { fr[y * N + c] = cscale(v, scale); };
+  };
+  mode_loop<N, C, true, true, NEAR, true>(p.k, buf, tw, hn, gather, store_for);
 }
 
 // ---------------------------------------------------------------------------
 // Probe numerator / weight, object gather and updates
 // ---------------------------------------------------------------------------
-
-// blockIdx.y < K: N_P,k(pix) = sum_b X[b][k][pix]; blockIdx.y == K: V(pix) = sum_b |o_b(pix)|^2
-// and its per-block maximum.  Slots are summed in ascending order (4 running
-// sums over b mod 4, combined in a fixed tree).
-__global__ __launch_bounds__(kThreads) void k_probe_accum(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                          int ns) {
-  __shared__ int2 bp[kMaxBatch];
-  __shared__ float red[kThreads];
-  const int n = p.n;
-  const size_t nn = (size_t)n * n;
-  const int pix = blockIdx.x * kThreads + threadIdx.x;
-  const int k = blockIdx.y;
-  if (k < p.k) {
-    if (pix >= n * n) return;
-    const float2* x = d.X + (size_t)k * nn + pix;
-    const size_t st = (size_t)p.k * nn;
-    float2 s0 = make_float2(0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
-    int b = 0;
-    for (; b + 4 <= ns; b += 4) {
-      s0 = cadd(s0, x[(size_t)b * st]);
-      s1 = cadd(s1, x[(size_t)(b + 1) * st]);
-      s2 = cadd(s2, x[(size_t)(b + 2) * st]);
-      s3 = cadd(s3, x[(size_t)(b + 3) * st]);
-    }
-    for (; b < ns; ++b) s0 = cadd(s0, x[(size_t)b * st]);
-    d.nP[(size_t)k * nn + pix] = cadd(cadd(s0, s1), cadd(s2, s3));
-    return;
-  }
-  for (int b = threadIdx.x; b < ns; b += kThreads) bp[b] = d.pos[slots[b]];
-  __syncthreads();
-  float vmax = 0.f;
-  if (pix < n * n) {
-    const int y = pix / n, x = pix - y * n;
-    float v0 = 0.f, v1 = 0.f;
-    int b = 0;
-    for (; b + 2 <= ns; b += 2) {
-      const float2 o0 = d.obj[(size_t)(bp[b].x + y) * p.w_obj + bp[b].y + x];
-      const float2 o1 = d.obj[(size_t)(bp[b + 1].x + y) * p.w_obj + bp[b + 1].y + x];
-      v0 += o0.x * o0.x + o0.y * o0.y;
-      v1 += o1.x * o1.x + o1.y * o1.y;
-    }
-    if (b < ns) {
-      const float2 o0 = d.obj[(size_t)(bp[b].x + y) * p.w_obj + bp[b].y + x];
-      v0 += o0.x * o0.x + o0.y * o0.y;
-    }
-    const float v = v0 + v1;
-    d.V[pix] = v;
-    vmax = v;
-  }
-  const float m = block_max_f(vmax, red);
-  if (threadIdx.x == 0) d.maxv_part[blockIdx.x] = m;
-}
 
 // Ascending list of the slots whose boxes intersect the object tile
 // [r0, r0+T) x [c0, c0+T); returns the list length (uniform).  ns <= 256.
@@ -401,37 +369,84 @@ __device__ __forceinline__ int tile_list(const DevBufs& d, const int* slots, int
   return total;
 }
 
-__global__ __launch_bounds__(kThreads) void k_obj_wmax(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns) {
-  __shared__ TileList tl;
-  __shared__ float red[kThreads];
-  const int n = p.n;
-  const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
-  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-  const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
-  if (cnt == 0) {
-    if (threadIdx.x == 0) d.maxw_part[tile] = 0.f;
-    return;
-  }
-  float m = 0.f;
-  for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
-    const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
-    if (r >= p.h_obj || c >= p.w_obj) continue;
-    float w = 0.f;
-    for (int i = 0; i < cnt; ++i) {
-      const int yy = r - tl.pos[i].x, xx = c - tl.pos[i].y;
-      if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) w += d.pw[yy * n + xx];
-    }
-    m = fmaxf(m, w);
-  }
-  m = block_max_f(m, red);
-  if (threadIdx.x == 0) d.maxw_part[tile] = m;
-}
-
 __device__ __forceinline__ float reduce_max_parts(const float* parts, int count, float* red) {
   float m = 0.f;
   for (int i = threadIdx.x; i < count; i += kThreads) m = fmaxf(m, parts[i]);
   return block_max_f(m, red);
+}
+
+// Pixels of a 32 x 32 object tile handled by one thread: rows r0 + ty + 8q, column c0 + tx.
+constexpr int kTileRowsPerPass = kThreads / kObjTile;
+constexpr int kTilePix = kObjTile * kObjTile / kThreads;
+
+struct SideScratch {
+  TileList tl;
+  float red[kThreads / 64];
+  int2 bp[kMaxBatch];
+};
+
+// Side work of the first pass of a batch (runs in extra blocks of k_fwd_rows,
+// before any update of the batch): job < tiles: the maximum over one object
+// tile of W(r) = sum_b sum_k |P_k(r - r_b)|^2; next jobs (probe update only):
+// V(pix) = sum_b |o_b(pix)|^2 over one block of probe pixels and its maximum.
+__device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
+                         SideScratch& sc) {
+  const int n = p.n;
+  const int tiles_x = (p.w_obj + kObjTile - 1) / kObjTile;
+  const int tiles = tiles_x * ((p.h_obj + kObjTile - 1) / kObjTile);
+  if (job < tiles) {
+    const int r0 = (job / tiles_x) * kObjTile, c0 = (job % tiles_x) * kObjTile;
+    const int cnt = tile_list(d, slots, ns, n, r0, c0, sc.tl);
+    if (cnt == 0) {
+      if (threadIdx.x == 0) d.maxw_part[job] = 0.f;
+      return;
+    }
+    const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
+    float w[kTilePix];
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) w[q] = 0.f;
+    for (int i = 0; i < cnt; ++i) {
+      const int2 rc = sc.tl.pos[i];
+      const int xx = c0 + tx - rc.y;
+#pragma unroll
+      for (int q = 0; q < kTilePix; ++q) {
+        const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
+        if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) w[q] += d.pw[yy * n + xx];
+      }
+    }
+    float m = 0.f;
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) m = fmaxf(m, w[q]);
+    m = block_max_f(m, sc.red);
+    if (threadIdx.x == 0) d.maxw_part[job] = m;
+    return;
+  }
+  const int vb = job - tiles;
+  if (!with_v || vb >= n_probe_blocks_dev(n)) return;
+  for (int b = threadIdx.x; b < ns; b += kThreads) sc.bp[b] = d.pos[slots[b]];
+  __syncthreads();
+  const int pix = vb * kThreads + threadIdx.x;
+  float vmax = 0.f;
+  if (pix < n * n) {
+    const int y = pix / n, x = pix - y * n;
+    float v0 = 0.f, v1 = 0.f;
+    int b = 0;
+    for (; b + 2 <= ns; b += 2) {
+      const float2 o0 = d.obj[(size_t)(sc.bp[b].x + y) * p.w_obj + sc.bp[b].y + x];
+      const float2 o1 = d.obj[(size_t)(sc.bp[b + 1].x + y) * p.w_obj + sc.bp[b + 1].y + x];
+      v0 += o0.x * o0.x + o0.y * o0.y;
+      v1 += o1.x * o1.x + o1.y * o1.y;
+    }
+    if (b < ns) {
+      const float2 o0 = d.obj[(size_t)(sc.bp[b].x + y) * p.w_obj + sc.bp[b].y + x];
+      v0 += o0.x * o0.x + o0.y * o0.y;
+    }
+    const float v = v0 + v1;
+    d.V[pix] = v;
+    vmax = v;
+  }
+  const float m = block_max_f(vmax, sc.red);
+  if (threadIdx.x == 0) d.maxv_part[vb] = m;
 }
 
 // Object update (gathered per tile, slots in ascending order).  Inside a
@@ -440,8 +455,8 @@ __device__ __forceinline__ float reduce_max_parts(const float* parts, int count,
 __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d, const int* __restrict__ slots,
                                                          int ns, int cc_sums, DebugPtrs dbg) {
   __shared__ TileList tl;
-  __shared__ float red[kThreads];
-  __shared__ double redd[kThreads];
+  __shared__ float red[kThreads / 64];
+  __shared__ double redd[kThreads / 64];
   const int n = p.n;
   const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
@@ -452,39 +467,53 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d,
   }
   const float maxw = reduce_max_parts(d.maxw_part, gridDim.x * gridDim.y, red);
   const size_t nn = (size_t)n * n;
-  float sa = 0.f, sp = 0.f;
-  for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
-    const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
-    if (r >= p.h_obj || c >= p.w_obj) continue;
-    float w = 0.f;
-    float2 num = make_float2(0.f, 0.f);
-    int mult = 0;
-    for (int i = 0; i < cnt; ++i) {
-      const int yy = r - tl.pos[i].x, xx = c - tl.pos[i].y;
+  const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
+  float w[kTilePix];
+  float2 num[kTilePix];
+  int mult[kTilePix];
+#pragma unroll
+  for (int q = 0; q < kTilePix; ++q) {
+    w[q] = 0.f;
+    num[q] = make_float2(0.f, 0.f);
+    mult[q] = 0;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    const int2 rc = tl.pos[i];
+    const float2* dOb = d.dO + (size_t)tl.slot[i] * nn;
+    const int xx = c0 + tx - rc.y;
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) {
+      const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
       if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) {
-        w += d.pw[yy * n + xx];
-        num = cadd(num, d.dO[(size_t)tl.slot[i] * nn + yy * n + xx]);
-        ++mult;
+        w[q] += d.pw[yy * n + xx];
+        num[q] = cadd(num[q], dOb[yy * n + xx]);
+        ++mult[q];
       }
     }
-    if (!mult) continue;
+  }
+  float sa = 0.f, sp = 0.f;
+  const int c = c0 + tx;
+#pragma unroll
+  for (int q = 0; q < kTilePix; ++q) {
+    const int r = r0 + ty + q * kTileRowsPerPass;
+    if (!mult[q] || r >= p.h_obj || c >= p.w_obj) continue;
     const size_t oi = (size_t)r * p.w_obj + c;
     if (dbg.n_obj) {
-      dbg.n_obj[oi] = num;
-      dbg.w_obj[oi] = w;
+      dbg.n_obj[oi] = num[q];
+      dbg.w_obj[oi] = w[q];
     }
     float2 o = d.obj[oi];
-    const float den = (1.0f - p.gamma_obj) * w + p.gamma_obj * maxw;
+    const float den = (1.0f - p.gamma_obj) * w[q] + p.gamma_obj * maxw;
     if (den > 0.f) {
       const float s = p.obj_step / den;
-      o.x += s * num.x;
-      o.y += s * num.y;
+      o.x += s * num[q].x;
+      o.y += s * num[q].y;
       d.obj[oi] = o;
     }
     if (cc_sums) {
       const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
-      sa += mult * fabsf(logf(a));
-      sp += mult * fabsf(atan2f(o.y, o.x));
+      sa += mult[q] * fabsf(logf(a));
+      sp += mult[q] * fabsf(atan2f(o.y, o.x));
     }
   }
   if (cc_sums) {
@@ -494,68 +523,82 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d,
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_probe_update(DevParams p, DevBufs d, int nparts) {
-  __shared__ float red[kThreads];
-  const float maxv = reduce_max_parts(d.maxv_part, nparts, red);
-  const int n = p.n;
-  const size_t nn = (size_t)n * n;
-  const int pix = blockIdx.x * kThreads + threadIdx.x;
-  if (pix >= n * n) return;
-  const float den = (1.0f - p.gamma_probe) * d.V[pix] + p.gamma_probe * maxv;
-  float pw = 0.f;
-  for (int k = 0; k < p.k; ++k) {
-    float2 v = d.probe[(size_t)k * nn + pix];
-    if (den > 0.f) {
-      const float s = p.probe_step / den;
-      const float2 np = d.nP[(size_t)k * nn + pix];
-      v.x += s * np.x;
-      v.y += s * np.y;
-      d.probe[(size_t)k * nn + pix] = v;
-    }
-    pw += v.x * v.x + v.y * v.y;
-  }
-  d.pw[pix] = pw;
-}
-
-__global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
-  const int n = p.n;
-  const size_t nn = (size_t)n * n;
-  const int pix = blockIdx.x * kThreads + threadIdx.x;
-  if (pix >= n * n) return;
-  float pw = 0.f;
-  for (int k = 0; k < p.k; ++k) {
-    const float2 v = d.probe[(size_t)k * nn + pix];
-    pw += v.x * v.x + v.y * v.y;
-  }
-  d.pw[pix] = pw;
-}
-
-// ---------------------------------------------------------------------------
-// Box 2: complex constraint, Eq. (9)-(11), over the union of the batch boxes
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kThreads) void k_cc_apply(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns) {
+// The updates that follow the object update in one launch:
+//  blocks [0, probe_blocks): probe numerator N_P,k = sum_b X[b][k] (slots in
+//    ascending order) and the probe update P_k += beta N_P,k / ((1-g) V + g max V),
+//    then sum_k |P_k|^2.  KP threads per pixel (KP = K rounded up to a power of 2).
+//  blocks [probe_blocks, probe_blocks + tiles): the complex constraint, Eq. (9)-(10),
+//    on the tile's pixels that lie in the union of the batch boxes.
+__global__ __launch_bounds__(kThreads) void k_post(DevParams p, DevBufs d, const int* __restrict__ slots, int ns,
+                                                   int probe_blocks, int kp, int cc_tiles) {
   __shared__ TileList tl;
-  __shared__ double red[kThreads];
+  __shared__ float red[kThreads / 64];
+  __shared__ double redd[kThreads / 64];
+  __shared__ float pk2[kThreads];
   const int n = p.n;
-  const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
+  const size_t nn = (size_t)n * n;
+  if ((int)blockIdx.x < probe_blocks) {
+    const float maxv = reduce_max_parts(d.maxv_part, n_probe_blocks_dev(n), red);
+    const int px_per = kThreads / kp;
+    const int k = threadIdx.x / px_per, px = threadIdx.x % px_per;
+    const int pix = blockIdx.x * px_per + px;
+    float mag2 = 0.f;
+    if (k < p.k && pix < n * n) {
+      const float2* x = d.X + (size_t)k * nn + pix;
+      const size_t st = (size_t)p.k * nn;
+      float2 s0 = make_float2(0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
+      int b = 0;
+      for (; b + 4 <= ns; b += 4) {
+        s0 = cadd(s0, x[(size_t)b * st]);
+        s1 = cadd(s1, x[(size_t)(b + 1) * st]);
+        s2 = cadd(s2, x[(size_t)(b + 2) * st]);
+        s3 = cadd(s3, x[(size_t)(b + 3) * st]);
+      }
+      for (; b < ns; ++b) s0 = cadd(s0, x[(size_t)b * st]);
+      const float2 np = cadd(cadd(s0, s1), cadd(s2, s3));
+      d.nP[(size_t)k * nn + pix] = np;
+      const float den = (1.0f - p.gamma_probe) * d.V[pix] + p.gamma_probe * maxv;
+      float2 v = d.probe[(size_t)k * nn + pix];
+      if (den > 0.f) {
+        const float sc = p.probe_step / den;
+        v.x += sc * np.x;
+        v.y += sc * np.y;
+        d.probe[(size_t)k * nn + pix] = v;
+      }
+      mag2 = v.x * v.x + v.y * v.y;
+    }
+    pk2[threadIdx.x] = mag2;
+    __syncthreads();
+    if (k == 0 && pix < n * n) {
+      float pw = 0.f;
+      for (int kk = 0; kk < p.k; ++kk) pw += pk2[kk * px_per + px];
+      d.pw[pix] = pw;
+    }
+    return;
+  }
+  // complex constraint on one object tile
+  const int tile = blockIdx.x - probe_blocks;
+  if (tile >= cc_tiles) return;
+  const int tiles_x = (p.w_obj + kObjTile - 1) / kObjTile;
+  const int r0 = (tile / tiles_x) * kObjTile, c0 = (tile % tiles_x) * kObjTile;
   const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
   if (cnt == 0) return;
   double sa = 0.0, sp = 0.0;
-  const int parts = gridDim.x * gridDim.y;
-  for (int i = threadIdx.x; i < parts; i += kThreads) {
+  for (int i = threadIdx.x; i < cc_tiles; i += kThreads) {
     sa += d.cc_part[i].x;
     sp += d.cc_part[i].y;
   }
-  sa = block_sum_d(sa, red);
-  sp = block_sum_d(sp, red);
+  sa = block_sum_d(sa, redd);
+  sp = block_sum_d(sp, redd);
   if (!(sp > 0.0)) return;
   float cbar = (float)(sa / sp);
   cbar = fminf(fmaxf(cbar, p.cbar_min), p.cbar_max);
   const float inv_c = 1.0f / cbar;
-  for (int e = threadIdx.x; e < kObjTile * kObjTile; e += kThreads) {
-    const int r = r0 + e / kObjTile, c = c0 + e % kObjTile;
+  const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
+  const int c = c0 + tx;
+#pragma unroll
+  for (int q = 0; q < kTilePix; ++q) {
+    const int r = r0 + ty + q * kTileRowsPerPass;
     if (r >= p.h_obj || c >= p.w_obj) continue;
     bool cov = false;
     for (int i = 0; i < cnt && !cov; ++i) {
@@ -573,6 +616,19 @@ __global__ __launch_bounds__(kThreads) void k_cc_apply(DevParams p, DevBufs d, c
     sincosf(pc, &sn, &cs);
     d.obj[oi] = make_float2(ac * cs, ac * sn);
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
+  const int n = p.n;
+  const size_t nn = (size_t)n * n;
+  const int pix = blockIdx.x * kThreads + threadIdx.x;
+  if (pix >= n * n) return;
+  float pw = 0.f;
+  for (int k = 0; k < p.k; ++k) {
+    const float2 v = d.probe[(size_t)k * nn + pix];
+    pw += v.x * v.x + v.y * v.y;
+  }
+  d.pw[pix] = pw;
 }
 
 // ---------------------------------------------------------------------------
@@ -804,11 +860,16 @@ bool supported_n(int n) {
   }
 
 template <int N, bool NEAR>
-static hipError_t fwd_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
+static hipError_t fwd_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool with_v,
                              hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
-  const size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
-  hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(N / L, bmax), dim3(kThreads), sh, s, p, d, slots, ns);
+  size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
+  if (sh < sizeof(SideScratch)) sh = sizeof(SideScratch);
+  const int gx = N / L;
+  const int jobs = n_obj_tiles(p) + (with_v ? n_probe_blocks(N) : 0);
+  const int side_rows = (jobs + gx - 1) / gx;
+  hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(gx, ns + side_rows), dim3(kThreads), sh, s, p, d, slots, ns,
+                     with_v ? 1 : 0);
   return hipGetLastError();
 }
 template <int N, bool NEAR>
@@ -842,10 +903,10 @@ static int cols_t() {
 }
 
 hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           int bmax, hipStream_t s) {
+                           bool with_v, hipStream_t s) {
 #define PTY_CASE(N) \
   case N:           \
-    return near ? fwd_rows_t<N, true>(p, d, slots, ns, bmax, s) : fwd_rows_t<N, false>(p, d, slots, ns, bmax, s);
+    return near ? fwd_rows_t<N, true>(p, d, slots, ns, with_v, s) : fwd_rows_t<N, false>(p, d, slots, ns, with_v, s);
   PTY_DISPATCH_N(n, PTY_CASE)
 #undef PTY_CASE
 }
@@ -891,33 +952,27 @@ int n_obj_tiles(const DevParams& p) {
 }
 int n_probe_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
 
-hipError_t launch_probe_accum(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
-  hipLaunchKernelGGL(k_probe_accum, dim3(n_probe_blocks(p.n), p.k + 1), dim3(kThreads), 0, s, p, d, slots, ns);
-  return hipGetLastError();
-}
 static dim3 obj_grid(const DevParams& p) {
   return dim3((p.w_obj + kObjTile - 1) / kObjTile, (p.h_obj + kObjTile - 1) / kObjTile);
-}
-hipError_t launch_obj_wmax(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
-  hipLaunchKernelGGL(k_obj_wmax, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns);
-  return hipGetLastError();
 }
 hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool cc_sums,
                              const DebugPtrs& dbg, hipStream_t s) {
   hipLaunchKernelGGL(k_obj_update, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, cc_sums ? 1 : 0, dbg);
   return hipGetLastError();
 }
-hipError_t launch_probe_update(const DevParams& p, const DevBufs& d, hipStream_t s) {
-  const int nb = n_probe_blocks(p.n);
-  hipLaunchKernelGGL(k_probe_update, dim3(nb), dim3(kThreads), 0, s, p, d, nb);
+hipError_t launch_post(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool probe, bool cc,
+                       hipStream_t s) {
+  int kp = 1;
+  while (kp < p.k) kp <<= 1;
+  const int px_per = kThreads / kp;
+  const int pb = probe ? (p.n * p.n + px_per - 1) / px_per : 0;
+  const int tiles = cc ? n_obj_tiles(p) : 0;
+  if (pb + tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_post, dim3(pb + tiles), dim3(kThreads), 0, s, p, d, slots, ns, pb, kp, tiles);
   return hipGetLastError();
 }
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
-  return hipGetLastError();
-}
-hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s) {
-  hipLaunchKernelGGL(k_cc_apply, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns);
   return hipGetLastError();
 }
 hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s) {

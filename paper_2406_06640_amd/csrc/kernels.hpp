@@ -37,7 +37,7 @@ struct DevBufs {
   float2* dO;         // [B][N][N] per-slot object numerator sum_k conj(P_k) dpsi_k
   float2* nP;         // [K][N][N] probe numerator
   float* V;           // [N][N] probe weight sum_b |o_b|^2
-  float* maxv_part;   // per-block max of V
+  float* maxv_part;   // per-block max of V (one per 256 probe pixels)
   float* maxw_part;   // per-object-tile max of W
   double* err_part;   // [n_pos][column blocks per frame] data-error partial sums
   double2* cc_part;   // [object tiles] (sum |ln A|, sum |phi|) weighted by box multiplicity
@@ -55,25 +55,23 @@ struct DebugPtrs {
 
 // Kernel classes (for timing).
 enum KernelClass {
-  KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_PROBE_ACC, KC_OBJ_WMAX, KC_OBJ_UPDATE,
-  KC_PROBE_UPDATE, KC_CC_APPLY, KC_GRAM, KC_EIG, KC_REMIX, KC_ERR, KC_COUNT
+  KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_POST, KC_GRAM, KC_EIG, KC_REMIX,
+  KC_ERR, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
 // Launchers.  Each returns the hipGetLastError() after the launch.
 hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           int bmax, hipStream_t s);
+                           bool with_v, hipStream_t s);
 hipError_t launch_fwd_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s);
 hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
                            const DebugPtrs& dbg, hipStream_t s);
 hipError_t launch_inv_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
                            int bmax, const DebugPtrs& dbg, hipStream_t s);
-hipError_t launch_probe_accum(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s);
-hipError_t launch_obj_wmax(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s);
 hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool cc_sums,
                              const DebugPtrs& dbg, hipStream_t s);
-hipError_t launch_probe_update(const DevParams& p, const DevBufs& d, hipStream_t s);
-hipError_t launch_cc_apply(const DevParams& p, const DevBufs& d, const int* slots, int ns, hipStream_t s);
+hipError_t launch_post(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool probe, bool cc,
+                       hipStream_t s);
 hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s);
 hipError_t launch_eig(const DevParams& p, const DevBufs& d, hipStream_t s);
 hipError_t launch_remix(const DevParams& p, const DevBufs& d, hipStream_t s);

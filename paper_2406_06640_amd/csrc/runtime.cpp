@@ -185,16 +185,13 @@ ptycho_status run_batch(ptycho_ctx* c, const int* d_slots, int ns, int t, const 
   hipStream_t s = c->stream;
   const int bm = ns;  // grid sized to the batch
   const bool cc = in_window(c->prm, t);
-  LAUNCH(c, KC_FWD_ROWS, launch_fwd_rows(p.n, near, p, d, d_slots, ns, bm, s));
+  const bool probe = t >= c->prm.probe_update_start;
+  LAUNCH(c, KC_FWD_ROWS, launch_fwd_rows(p.n, near, p, d, d_slots, ns, probe, s));
   LAUNCH(c, KC_FWD_COLS, launch_fwd_cols(p.n, near, p, d, ns, bm, s));
   LAUNCH(c, KC_INV_COLS, launch_inv_cols(p.n, near, p, d, d_slots, ns, bm, dbg, s));
   LAUNCH(c, KC_INV_ROWS, launch_inv_rows(p.n, near, p, d, d_slots, ns, bm, dbg, s));
-  const bool probe = t >= c->prm.probe_update_start;
-  if (probe) LAUNCH(c, KC_PROBE_ACC, launch_probe_accum(p, d, d_slots, ns, s));
-  LAUNCH(c, KC_OBJ_WMAX, launch_obj_wmax(p, d, d_slots, ns, s));
   LAUNCH(c, KC_OBJ_UPDATE, launch_obj_update(p, d, d_slots, ns, cc, dbg, s));
-  if (probe) LAUNCH(c, KC_PROBE_UPDATE, launch_probe_update(p, d, s));
-  if (cc) LAUNCH(c, KC_CC_APPLY, launch_cc_apply(p, d, d_slots, ns, s));
+  if (probe || cc) LAUNCH(c, KC_POST, launch_post(p, d, d_slots, ns, probe, cc, s));
   return PTYCHO_OK;
 }
 
