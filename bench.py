@@ -127,6 +127,8 @@ def main():
     ctx = P.ptycho_init(cp, inten, pos, probe0, obj0, P.PTYCHO_MEM_DEVICE, stream)
     names = P.kernel_names()
     try:
+        col_variant = P.ptycho_autotune(ctx, trials=3)
+        print(f"[bench] autotuned column-tile variant {col_variant}", file=sys.stderr, flush=True)
         P.ptycho_iterate(ctx, args.warmup)
         # one profiled iteration (events around every launch) to find the dominant kernel
         P.ptycho_set_timing(ctx, (1 << len(names)) - 1)
@@ -179,7 +181,8 @@ def main():
                                "(1600 positions), K=4 modes, 5 wavelengths +-2.5%, sigma=2, Poisson 1e6; "
                                f"pc-ePIE batch {args.batch}, 11x11 blur, complex constraint and "
                                "orthogonalisation on every timed iteration",
-                   "positions": n_pos, "modes": k, "frame": n, "batch": args.batch},
+                   "positions": n_pos, "modes": k, "frame": n, "batch": args.batch,
+                   "column_tile_variant": col_variant},
         "roofline": roof,
         "kernel_ms_per_step": {nm: round(ms, 4) for nm, (ms, c) in prof.items() if c},
         "final_data_error": float(errs[-1]),

@@ -136,6 +136,23 @@ ptycho_status ptycho_debug_step(ptycho_ctx* ctx, const int32_t* idx, int32_t B, 
                                 float* psi, float* psi_new, float* factor, float* n_obj,
                                 float* w_obj, float* n_probe, float* v_probe, int32_t mem_kind);
 
+/* Replay each iteration from a HIP graph captured on first use (enable != 0)
+ * instead of launching its kernels one by one; the graph is rebuilt when the
+ * column-tile choice changes.  Results are bitwise identical either way.
+ * Not used while per-kernel timing is on. */
+ptycho_status ptycho_set_graph(ptycho_ctx* ctx, int32_t enable);
+
+/* Column-tile autotuner: times each supported column-block width of the
+ * column passes on the context's first batch (`trials` timed repetitions
+ * each), keeps the fastest and writes its index (0..2) to *chosen (may be
+ * NULL).  The object and probe are restored afterwards.  Choices are cached
+ * per (n, n_modes, batch, geometry) for the process and, when the environment
+ * variable PTYCHO_TUNE_CACHE names a file, appended to it and read back by
+ * later processes; force != 0 re-times a cached entry.  The object and probe
+ * after any iteration are bitwise identical for every choice (the data error
+ * E_t is summed in a different grouping). */
+ptycho_status ptycho_autotune(ptycho_ctx* ctx, int32_t trials, int32_t force, int32_t* chosen);
+
 /* Per-kernel timing with HIP events recorded on the context stream around each
  * launch of the kernel classes selected by `mask` (bit i = class i, see
  * ptycho_kernel_name); 0 disables.  Totals accumulate until reset. */
@@ -153,6 +170,22 @@ void ptycho_destroy(ptycho_ctx* ctx);
 /* Text of the last error on this context, or of this thread's last failed
  * ptycho_init / NULL-context call when ctx is NULL.  Never NULL. */
 const char* ptycho_last_error(const ptycho_ctx* ctx);
+
+/* Groups of independent reconstructions (many cases of uneven frame size,
+ * position count and mode count advanced together).  Every pass of a batch
+ * runs as one launch per (frame size, geometry) class covering the batch of
+ * that index of every case in the class; a case's results are bitwise
+ * identical to running it alone with ptycho_iterate(ctx, n, NULL, ...).
+ * The contexts must share one device and stream and stay alive while the
+ * group exists; the group does not own them. */
+typedef struct ptycho_group ptycho_group;
+ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_group** out);
+/* n_iter iterations of every case, each in its own generated order (seed XOR t).
+ * err_out (host, may be NULL): [n cases][n_iter] data errors.  A case whose
+ * error is non-finite is marked failed and PTYCHO_E_NUMERIC returned. */
+ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_out);
+void ptycho_group_destroy(ptycho_group* g);
+const char* ptycho_group_last_error(const ptycho_group* g);
 
 /* Host-only: the order used for iteration t when none is given -- Fisher-Yates
  * over 0..n_pos-1 (for i = n_pos-1 .. 1: j = next % (i + 1), swap) with `next`

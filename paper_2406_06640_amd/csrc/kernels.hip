@@ -39,13 +39,21 @@ constexpr int largest_divisor_le(int n, int cap) {
   return best;
 }
 
-// Lines per block: ~4096 elements (16 per thread) for row and column blocks.
+// Lines per block: ~4096 elements (16 per thread) for row blocks; column blocks
+// take COLS columns (variant 1) or half / twice as many (variants 0 / 2, chosen
+// by the autotuner when they divide N and stay within 64 columns).
 template <int N>
 struct Cfg {
   static constexpr int ROWS = largest_divisor_le(N, 4096 / N < 1 ? 1 : 4096 / N);
   static constexpr int CCAP = 4096 / N < 4 ? 4 : (4096 / N > 64 ? 64 : 4096 / N);
   static constexpr int COLS = largest_divisor_le(N, CCAP);
   static_assert(N % ROWS == 0 && N % COLS == 0, "tile must divide N");
+};
+template <int N, int V>
+struct ColW {
+  static constexpr int W0 = V == 0 ? Cfg<N>::COLS / 2 : (V == 2 ? Cfg<N>::COLS * 2 : Cfg<N>::COLS);
+  static constexpr bool VALID = W0 >= 1 && W0 <= 64 && N % W0 == 0;
+  static constexpr int C = VALID ? W0 : Cfg<N>::COLS;
 };
 
 // Block reductions in a fixed order: butterfly over the 64 lanes of each wave,
@@ -70,9 +78,26 @@ __device__ __forceinline__ float block_max_f(float v, float* sh) {
 
 __host__ __device__ __forceinline__ int n_probe_blocks_dev(int n) { return (n * n + kThreads - 1) / kThreads; }
 
-// ---------------------------------------------------------------------------
-// Row passes (lines along x; Frame<N, L, false>)
-// ---------------------------------------------------------------------------
+// The batch a block works on: case blockIdx.y of the table, batch `beta` of
+// iteration `it`.  False when the case has no such batch.
+struct Batch {
+  const CaseDesc* cs;
+  const int* slots;
+  int ns;
+  int flags;
+};
+
+__device__ __forceinline__ bool open_batch(const CaseDesc* cases, int beta, const int* it_ptr, Batch& bt) {
+  const int it = *it_ptr;
+  bt.cs = cases + blockIdx.y;
+  const int nb = bt.cs->n_batches;
+  if (beta >= nb) return false;
+  const int np = bt.cs->n_pos, B = bt.cs->batch;
+  bt.slots = bt.cs->order + (size_t)it * np + (size_t)beta * B;
+  bt.ns = min(B, np - beta * B);
+  bt.flags = bt.cs->flags[it];
+  return true;
+}
 
 // One 1D pass over the K modes of a block's lines, with the next mode's inputs
 // gathered while the current mode is in its LDS stages.  gather(k, v) fills the
@@ -114,33 +139,43 @@ __device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots,
                          SideScratch& sc);
 
 // Blocks with blockIdx.y >= ns do the batch's side work (see side_job).
+struct SideScratch;
+__device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
+                         SideScratch& sc);
+
+// Row pass 1.  Blocks past the case's slots do the batch's side work (side_job).
 template <int N, bool NEAR>
-__global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns, int with_v) {
+__global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   constexpr int L = Cfg<N>::ROWS;
   constexpr int LS = RegShape<N, L>::LOAD_SLOTS;
+  constexpr int GX = N / L;
   extern __shared__ float2 sm[];
-  float2* tw = sm;
-  float2* hn = sm + N;
-  float2* buf = sm + 2 * N;
-  const int b = blockIdx.y;
-  if (b >= ns) {
-    side_job(p, d, slots, ns, (b - ns) * gridDim.x + blockIdx.x, with_v != 0,
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  if (b >= bt.ns) {
+    side_job(p, d, bt.slots, bt.ns, (b - bt.ns) * GX + bx, (bt.flags & FLAG_PROBE) != 0,
              *reinterpret_cast<SideScratch*>(sm));
     return;
   }
-  const int y0 = blockIdx.x * L;
-  const int2 rc = d.pos[slots[b]];
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* buf = sm + 2 * N;
+  const int y0 = bx * L;
+  const int2 rc = d.pos[bt.slots[b]];
   for (int i = threadIdx.x; i < N; i += kThreads) {
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
+  const int K = p.k, W = p.w_obj;
   float2 o[LS];
-  const float2* orow = d.obj + (size_t)(rc.x + y0) * p.w_obj + rc.y;
-  for_load_slots<N, L, false>([&](int s, int line, int pos) { o[s] = orow[line * p.w_obj + pos]; });
+  const float2* orow = d.obj + (size_t)(rc.x + y0) * W + rc.y;
+  for_load_slots<N, L, false>([&](int s, int line, int pos) { o[s] = orow[line * W + pos]; });
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   const float2* p0 = d.probe + (size_t)y0 * N;
-  float2* x0 = d.X + ((size_t)b * p.k * N + y0) * N;
+  float2* x0 = d.X + ((size_t)b * K * N + y0) * N;
   auto gather = [&](int k, float2* v) {
     const float2* pk = p0 + (size_t)k * N * N;
     auto load = [&](int s, int line, int pos) { return cmul(o[s], pk[line * N + pos]); };
@@ -150,36 +185,42 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(DevParams p, DevBufs d, c
     float2* out = x0 + (size_t)k * N * N;
     return [=](int s, int line, int pos, float2 v) { out[line * N + pos] = cscale(v, scale); };
   };
-  mode_loop<N, L, false, false, NEAR, false>(p.k, buf, tw, hn, gather, store_for);
+  mode_loop<N, L, false, false, NEAR, false>(K, buf, tw, hn, gather, store_for);
 }
 
 template <int N, bool NEAR>
-__global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns, DebugPtrs dbg) {
+__global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   constexpr int L = Cfg<N>::ROWS;
   constexpr int SS = RegShape<N, L>::STORE_SLOTS;
+  constexpr int GX = N / L;
   extern __shared__ float2 sm[];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  if (b >= bt.ns) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const DebugPtrs dbg = bt.cs->dbg;
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
-  const int b = blockIdx.y;
-  if (b >= ns) return;
-  const int y0 = blockIdx.x * L;
-  const int2 rc = d.pos[slots[b]];
+  const int y0 = bx * L;
+  const int2 rc = d.pos[bt.slots[b]];
   for (int i = threadIdx.x; i < N; i += kThreads) {
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
+  const int K = p.k, W = p.w_obj;
   // the box rows are re-read in every mode's epilogue (cache hits) rather than
-  // held in registers, which keeps the occupancy of this pass up
+  // held in registers, which keeps the register count of this pass down
   float2 acc[SS];
-  const float2* orow = d.obj + (size_t)(rc.x + y0) * p.w_obj + rc.y;
+  const float2* orow = d.obj + (size_t)(rc.x + y0) * W + rc.y;
 #pragma unroll
   for (int i = 0; i < SS; ++i) acc[i] = make_float2(0.f, 0.f);
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  float2* x0 = d.X + ((size_t)b * p.k * N + y0) * N;
+  float2* x0 = d.X + ((size_t)b * K * N + y0) * N;
   const float2* p0 = d.probe + (size_t)y0 * N;
-  float2* dbg0 = dbg.psi_new ? dbg.psi_new + ((size_t)b * p.k * N + y0) * N : nullptr;
+  float2* dbg0 = dbg.psi_new ? dbg.psi_new + ((size_t)b * K * N + y0) * N : nullptr;
   auto gather = [&](int k, float2* v) {
     const float2* fr = x0 + (size_t)k * N * N;
     auto load = [&](int s, int line, int pos) { return fr[line * N + pos]; };
@@ -192,14 +233,14 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(DevParams p, DevBufs d, c
     return [&, fr, pk, dbgp](int s, int line, int pos, float2 v) {
       const float2 psi_new = cscale(v, scale);
       const float2 pv = pk[line * N + pos];
-      const float2 o = orow[line * p.w_obj + pos];
+      const float2 o = orow[line * W + pos];
       const float2 dpsi = csub(psi_new, cmul(o, pv));
       acc[s] = cadd(acc[s], cmulc(dpsi, pv));  // conj(P) dpsi
       fr[line * N + pos] = cmulc(dpsi, o);       // conj(o) dpsi
       if (dbgp) dbgp[line * N + pos] = psi_new;
     };
   };
-  mode_loop<N, L, false, true, NEAR, true>(p.k, buf, tw, hn, gather, store_for);
+  mode_loop<N, L, false, true, NEAR, true>(K, buf, tw, hn, gather, store_for);
   float2* dO = d.dO + ((size_t)b * N + y0) * N;
   for_store_slots<N, L, false>([&](int s, int line, int pos) { dO[line * N + pos] = acc[s]; });
 }
@@ -217,26 +258,31 @@ __device__ __forceinline__ int wrap(int t, int n) {
 // Forward column transform of every mode, the incoherent mode sum, and the
 // vertical (sigma2) half of the separable Gaussian blur of Eq. (6) (or of the
 // intensity, Eq. 2): q = g_y (x) sqrt(sum_k |Psi_k|^2).
-template <int N, bool NEAR>
-__global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, int ns) {
-  constexpr int C = Cfg<N>::COLS;
+template <int N, bool NEAR, int C>
+__global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   constexpr int SS = RegShape<N, C>::STORE_SLOTS;
+  constexpr int GX = N / C;
   extern __shared__ float2 sm[];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  if (b >= bt.ns) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
-  const int b = blockIdx.y;
-  if (b >= ns) return;
-  const int x0 = blockIdx.x * C;
+  const int x0 = bx * C;
   for (int i = threadIdx.x; i < N; i += kThreads) {
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
+  const int K = p.k;
   float acc[SS];
 #pragma unroll
   for (int i = 0; i < SS; ++i) acc[i] = 0.f;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  float2* f0 = d.X + (size_t)b * p.k * N * N + x0;
+  float2* f0 = d.X + (size_t)b * K * N * N + x0;
   auto gather = [&](int k, float2* v) {
     const float2* fr = f0 + (size_t)k * N * N;
     auto load = [&](int s, int c, int y) { return fr[y * N + c]; };
@@ -250,39 +296,43 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(DevParams p, DevBufs d, i
       acc[s] += v.x * v.x + v.y * v.y;
     };
   };
-  mode_loop<N, C, true, false, NEAR, false>(p.k, buf, tw, hn, gather, store_for);
+  mode_loop<N, C, true, false, NEAR, false>(K, buf, tw, hn, gather, store_for);
   // vertical blur of the modelled amplitude (or intensity) over whole columns
   float* tile = reinterpret_cast<float*>(buf);
   constexpr int TS = C + 1;
-  for_store_slots<N, C, true>([&](int s, int c, int y) {
-    tile[y * TS + c] = p.blur_intensity ? acc[s] : sqrtf(acc[s]);
-  });
+  const bool inten = p.blur_intensity != 0;
+  for_store_slots<N, C, true>([&](int s, int c, int y) { tile[y * TS + c] = inten ? acc[s] : sqrtf(acc[s]); });
   __syncthreads();
   float* q = d.q + (size_t)b * N * N + x0;
   const int h = p.ks_half;
+  const float* gy = p.gy;
   for_store_slots<N, C, true>([&](int s, int c, int y) {
-    float g = p.gy[0] * tile[y * TS + c];
-    for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
+    float g = gy[0] * tile[y * TS + c];
+    for (int dy = 1; dy <= h; ++dy) g += gy[dy] * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
     q[y * N + c] = g;
   });
 }
 
 // Horizontal (sigma1) half of the blur, the modulus factor of box 1 and the
 // data error, then Psi' = factor Psi and the inverse column transform.
-template <int N, bool NEAR>
-__global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                       int ns, DebugPtrs dbg) {
-  constexpr int C = Cfg<N>::COLS;
+template <int N, bool NEAR, int C>
+__global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   constexpr int LS = RegShape<N, C>::LOAD_SLOTS;
+  constexpr int GX = N / C;
   extern __shared__ float2 sm[];
-  __shared__ double red[kThreads];
+  __shared__ double red[kThreads / 64];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  if (b >= bt.ns) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  float* dbg_factor = bt.cs->dbg.factor;
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
-  const int b = blockIdx.y;
-  if (b >= ns) return;
-  const int x0 = blockIdx.x * C;
-  const int pat = slots[b];
+  const int x0 = bx * C;
+  const int pat = bt.slots[b];
   for (int i = threadIdx.x; i < N; i += kThreads) {
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
@@ -297,28 +347,32 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, c
   float f[LS];
   double err = 0.0;
   const float* amp = d.amp + (size_t)pat * N * N + x0;
-  float* dbgf = dbg.factor ? dbg.factor + (size_t)b * N * N + x0 : nullptr;
+  float* dbgf = dbg_factor ? dbg_factor + (size_t)b * N * N + x0 : nullptr;
+  const bool inten = p.blur_intensity != 0;
+  const float eps = p.eps;
+  const float* gx = p.gx;
   for_load_slots<N, C, true>([&](int s, int c, int y) {
     const float* row = tile + y * TW + c + h;
-    float g = p.gx[0] * row[0];
-    for (int dx = 1; dx <= h; ++dx) g += p.gx[dx] * (row[-dx] + row[dx]);
+    float g = gx[0] * row[0];
+    for (int dx = 1; dx <= h; ++dx) g += gx[dx] * (row[-dx] + row[dx]);
     const float a = amp[y * N + c];
     float ag;
-    if (p.blur_intensity) {
+    if (inten) {
       ag = sqrtf(g);
-      f[s] = a / sqrtf(g + p.eps * p.eps);
+      f[s] = a / sqrtf(g + eps * eps);
     } else {
       ag = g;
-      f[s] = a / (g + p.eps);
+      f[s] = a / (g + eps);
     }
     if (dbgf) dbgf[y * N + c] = f[s];
     const double dd = (double)a - (double)ag;
     err += dd * dd;
   });
   const double tot = block_sum_d(err, red);  // also orders the tile reads before the FFT's LDS writes
-  if (threadIdx.x == 0) d.err_part[(size_t)pat * (N / C) + blockIdx.x] = tot;
+  if (threadIdx.x == 0) d.err_part[(size_t)pat * GX + bx] = tot;
+  const int K = p.k;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  float2* f0 = d.X + (size_t)b * p.k * N * N + x0;
+  float2* f0 = d.X + (size_t)b * K * N * N + x0;
   auto gather = [&](int k, float2* v) {
     const float2* fr = f0 + (size_t)k * N * N;
     auto load = [&](int s, int c, int y) { return cscale(fr[y * N + c], f[s]); };
@@ -328,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(DevParams p, DevBufs d, c
     float2* fr = f0 + (size_t)k * N * N;
     return [=](int s, int c, int y, float2 v) { fr[y * N + c] = cscale(v, scale); };
   };
-  mode_loop<N, C, true, true, NEAR, true>(p.k, buf, tw, hn, gather, store_for);
+  mode_loop<N, C, true, true, NEAR, true>(K, buf, tw, hn, gather, store_for);
 }
 
 // ---------------------------------------------------------------------------
@@ -375,6 +429,11 @@ __device__ __forceinline__ float reduce_max_parts(const float* parts, int count,
   return block_max_f(m, red);
 }
 
+__host__ __device__ __forceinline__ int tiles_x_of(const DevParams& p) { return (p.w_obj + kObjTile - 1) / kObjTile; }
+__host__ __device__ __forceinline__ int tiles_of(const DevParams& p) {
+  return tiles_x_of(p) * ((p.h_obj + kObjTile - 1) / kObjTile);
+}
+
 // Pixels of a 32 x 32 object tile handled by one thread: rows r0 + ty + 8q, column c0 + tx.
 constexpr int kTileRowsPerPass = kThreads / kObjTile;
 constexpr int kTilePix = kObjTile * kObjTile / kThreads;
@@ -392,8 +451,8 @@ struct SideScratch {
 __device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
                          SideScratch& sc) {
   const int n = p.n;
-  const int tiles_x = (p.w_obj + kObjTile - 1) / kObjTile;
-  const int tiles = tiles_x * ((p.h_obj + kObjTile - 1) / kObjTile);
+  const int tiles_x = tiles_x_of(p);
+  const int tiles = tiles_of(p);
   if (job < tiles) {
     const int r0 = (job / tiles_x) * kObjTile, c0 = (job % tiles_x) * kObjTile;
     const int cnt = tile_list(d, slots, ns, n, r0, c0, sc.tl);
@@ -452,20 +511,27 @@ __device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots,
 // Object update (gathered per tile, slots in ascending order).  Inside a
 // constraint window it also writes this tile's share of the C-bar sums of
 // Eq. (11): each pixel counted once per box that covers it.
-__global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d, const int* __restrict__ slots,
-                                                         int ns, int cc_sums, DebugPtrs dbg) {
+__global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   __shared__ TileList tl;
   __shared__ float red[kThreads / 64];
   __shared__ double redd[kThreads / 64];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const DebugPtrs dbg = bt.cs->dbg;
+  const int tiles = tiles_of(p), tiles_x = tiles_x_of(p);
+  const int tile = blockIdx.x;
+  if (tile >= tiles) return;
+  const bool cc_sums = (bt.flags & FLAG_CC) != 0;
   const int n = p.n;
-  const int r0 = blockIdx.y * kObjTile, c0 = blockIdx.x * kObjTile;
-  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-  const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
+  const int r0 = (tile / tiles_x) * kObjTile, c0 = (tile % tiles_x) * kObjTile;
+  const int cnt = tile_list(d, bt.slots, bt.ns, n, r0, c0, tl);
   if (cnt == 0) {
     if (cc_sums && threadIdx.x == 0) d.cc_part[tile] = make_double2(0.0, 0.0);
     return;
   }
-  const float maxw = reduce_max_parts(d.maxw_part, gridDim.x * gridDim.y, red);
+  const float maxw = reduce_max_parts(d.maxw_part, tiles, red);
   const size_t nn = (size_t)n * n;
   const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
   float w[kTilePix];
@@ -491,6 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d,
       }
     }
   }
+  const float gam = p.gamma_obj, step = p.obj_step;
   float sa = 0.f, sp = 0.f;
   const int c = c0 + tx;
 #pragma unroll
@@ -503,9 +570,9 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d,
       dbg.w_obj[oi] = w[q];
     }
     float2 o = d.obj[oi];
-    const float den = (1.0f - p.gamma_obj) * w[q] + p.gamma_obj * maxw;
+    const float den = (1.0f - gam) * w[q] + gam * maxw;
     if (den > 0.f) {
-      const float s = p.obj_step / den;
+      const float s = step / den;
       o.x += s * num[q].x;
       o.y += s * num[q].y;
       d.obj[oi] = o;
@@ -523,29 +590,46 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(DevParams p, DevBufs d,
   }
 }
 
+__host__ __device__ __forceinline__ int pow2_at_least(int k) {
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  return kp;
+}
+__host__ __device__ __forceinline__ int post_probe_blocks(int n, int k) {
+  const int px_per = kThreads / pow2_at_least(k);
+  return (n * n + px_per - 1) / px_per;
+}
+
 // The updates that follow the object update in one launch:
-//  blocks [0, probe_blocks): probe numerator N_P,k = sum_b X[b][k] (slots in
+//  blocks [0, probe blocks): probe numerator N_P,k = sum_b X[b][k] (slots in
 //    ascending order) and the probe update P_k += beta N_P,k / ((1-g) V + g max V),
 //    then sum_k |P_k|^2.  KP threads per pixel (KP = K rounded up to a power of 2).
-//  blocks [probe_blocks, probe_blocks + tiles): the complex constraint, Eq. (9)-(10),
-//    on the tile's pixels that lie in the union of the batch boxes.
-__global__ __launch_bounds__(kThreads) void k_post(DevParams p, DevBufs d, const int* __restrict__ slots, int ns,
-                                                   int probe_blocks, int kp, int cc_tiles) {
+//  next blocks, one per object tile: the complex constraint, Eq. (9)-(10), on
+//    the tile's pixels that lie in the union of the batch boxes.
+__global__ __launch_bounds__(kThreads) void k_post(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   __shared__ TileList tl;
   __shared__ float red[kThreads / 64];
   __shared__ double redd[kThreads / 64];
   __shared__ float pk2[kThreads];
-  const int n = p.n;
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const int n = p.n, K = p.k;
   const size_t nn = (size_t)n * n;
-  if ((int)blockIdx.x < probe_blocks) {
+  const bool probe = (bt.flags & FLAG_PROBE) != 0, cc = (bt.flags & FLAG_CC) != 0;
+  const int pb = probe ? post_probe_blocks(n, K) : 0;
+  const int tiles = tiles_of(p);
+  const int ns = bt.ns;
+  if ((int)blockIdx.x < pb) {
     const float maxv = reduce_max_parts(d.maxv_part, n_probe_blocks_dev(n), red);
-    const int px_per = kThreads / kp;
+    const int px_per = kThreads / pow2_at_least(K);
     const int k = threadIdx.x / px_per, px = threadIdx.x % px_per;
     const int pix = blockIdx.x * px_per + px;
     float mag2 = 0.f;
-    if (k < p.k && pix < n * n) {
+    if (k < K && pix < n * n) {
       const float2* x = d.X + (size_t)k * nn + pix;
-      const size_t st = (size_t)p.k * nn;
+      const size_t st = (size_t)K * nn;
       float2 s0 = make_float2(0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
       int b = 0;
       for (; b + 4 <= ns; b += 4) {
@@ -571,20 +655,20 @@ __global__ __launch_bounds__(kThreads) void k_post(DevParams p, DevBufs d, const
     __syncthreads();
     if (k == 0 && pix < n * n) {
       float pw = 0.f;
-      for (int kk = 0; kk < p.k; ++kk) pw += pk2[kk * px_per + px];
+      for (int kk = 0; kk < K; ++kk) pw += pk2[kk * px_per + px];
       d.pw[pix] = pw;
     }
     return;
   }
   // complex constraint on one object tile
-  const int tile = blockIdx.x - probe_blocks;
-  if (tile >= cc_tiles) return;
-  const int tiles_x = (p.w_obj + kObjTile - 1) / kObjTile;
+  const int tile = blockIdx.x - pb;
+  if (!cc || tile >= tiles) return;
+  const int tiles_x = tiles_x_of(p);
   const int r0 = (tile / tiles_x) * kObjTile, c0 = (tile % tiles_x) * kObjTile;
-  const int cnt = tile_list(d, slots, ns, n, r0, c0, tl);
+  const int cnt = tile_list(d, bt.slots, ns, n, r0, c0, tl);
   if (cnt == 0) return;
   double sa = 0.0, sp = 0.0;
-  for (int i = threadIdx.x; i < cc_tiles; i += kThreads) {
+  for (int i = threadIdx.x; i < tiles; i += kThreads) {
     sa += d.cc_part[i].x;
     sp += d.cc_part[i].y;
   }
@@ -594,6 +678,7 @@ __global__ __launch_bounds__(kThreads) void k_post(DevParams p, DevBufs d, const
   float cbar = (float)(sa / sp);
   cbar = fminf(fmaxf(cbar, p.cbar_min), p.cbar_max);
   const float inv_c = 1.0f / cbar;
+  const float a1 = p.alpha1, a2 = p.alpha2;
   const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
   const int c = c0 + tx;
 #pragma unroll
@@ -610,8 +695,8 @@ __global__ __launch_bounds__(kThreads) void k_post(DevParams p, DevBufs d, const
     const float2 o = d.obj[oi];
     const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
     const float phi = atan2f(o.y, o.x);
-    const float ac = expf((1.0f - p.alpha1) * lna + p.alpha1 * cbar * phi);
-    const float pc = (1.0f - p.alpha2) * phi + p.alpha2 * inv_c * lna;
+    const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
+    const float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
     float sn, cs;
     sincosf(pc, &sn, &cs);
     d.obj[oi] = make_float2(ac * cs, ac * sn);
@@ -632,21 +717,30 @@ __global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
 }
 
 // ---------------------------------------------------------------------------
-// Mode orthogonalisation (K > 1) and the data error
+// Mode orthogonalisation (K > 1) and the data error, per case
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_gram(DevParams p, DevBufs d) {
-  __shared__ double red[kThreads];
-  // blockIdx.y = pair index (i <= j), blockIdx.x = pixel chunk
-  int pair = blockIdx.y, i = 0;
-  while (pair >= p.k - i) {
-    pair -= p.k - i;
+__global__ __launch_bounds__(kThreads) void k_gram(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
+  __shared__ double red[kThreads / 64];
+  const CaseDesc* cs = cases + blockIdx.y;
+  if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
+  const DevParams& p = cs->p;
+  const DevBufs d = cs->d;
+  const int K = p.k;
+  // blockIdx.x = pair (i <= j) * kGramBlocks + pixel chunk
+  int pair = blockIdx.x / kGramBlocks;
+  const int chunk_id = blockIdx.x % kGramBlocks;
+  if (pair >= K * (K + 1) / 2) return;
+  const int pair_id = pair;
+  int i = 0;
+  while (pair >= K - i) {
+    pair -= K - i;
     ++i;
   }
   const int j = i + pair;
   const int nn = p.n * p.n;
   const int chunk = (nn + kGramBlocks - 1) / kGramBlocks;
-  const int lo = blockIdx.x * chunk, hi = min(nn, lo + chunk);
+  const int lo = chunk_id * chunk, hi = min(nn, lo + chunk);
   const float2* pi = d.probe + (size_t)i * nn;
   const float2* pj = d.probe + (size_t)j * nn;
   double re = 0.0, im = 0.0;
@@ -658,14 +752,17 @@ __global__ __launch_bounds__(kThreads) void k_gram(DevParams p, DevBufs d) {
   }
   re = block_sum_d(re, red);
   im = block_sum_d(im, red);
-  if (threadIdx.x == 0) d.gram_part[(size_t)blockIdx.y * kGramBlocks + blockIdx.x] = make_double2(re, im);
+  if (threadIdx.x == 0) d.gram_part[(size_t)pair_id * kGramBlocks + chunk_id] = make_double2(re, im);
 }
 
 // Hermitian eigendecomposition by cyclic complex Jacobi rotations (double),
 // one thread; K <= 16.
-__global__ void k_eig(DevParams p, DevBufs d) {
+__global__ void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int K = p.k;
+  const CaseDesc* cs = cases + blockIdx.y;
+  if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
+  const DevBufs d = cs->d;
+  const int K = cs->p.k;
   double ar[kMaxModes][kMaxModes], ai[kMaxModes][kMaxModes];
   double vr[kMaxModes][kMaxModes], vi[kMaxModes][kMaxModes];
   int pair = 0;
@@ -766,30 +863,36 @@ __global__ void k_eig(DevParams p, DevBufs d) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_remix(DevParams p, DevBufs d) {
-  const int n = p.n;
+__global__ __launch_bounds__(kThreads) void k_remix(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
+  const CaseDesc* cs = cases + blockIdx.y;
+  if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
+  const DevBufs d = cs->d;
+  const int n = cs->p.n, K = cs->p.k;
   const size_t nn = (size_t)n * n;
   const int pix = blockIdx.x * kThreads + threadIdx.x;
   if (pix >= n * n) return;
   float2 in[kMaxModes];
-  for (int i = 0; i < p.k; ++i) in[i] = d.probe[(size_t)i * nn + pix];
+  for (int i = 0; i < K; ++i) in[i] = d.probe[(size_t)i * nn + pix];
   float pw = 0.f;
-  for (int j = 0; j < p.k; ++j) {
+  for (int j = 0; j < K; ++j) {
     float2 s = make_float2(0.f, 0.f);
-    for (int i = 0; i < p.k; ++i) s = cadd(s, cmul(in[i], d.vmix[i * p.k + j]));
+    for (int i = 0; i < K; ++i) s = cadd(s, cmul(in[i], d.vmix[i * K + j]));
     d.probe[(size_t)j * nn + pix] = s;
     pw += s.x * s.x + s.y * s.y;
   }
   d.pw[pix] = pw;
 }
 
-__global__ __launch_bounds__(kThreads) void k_err_reduce(const double* __restrict__ part, int count,
-                                                         double inv_denom, float* out) {
-  __shared__ double red[kThreads];
+__global__ __launch_bounds__(kThreads) void k_err_reduce(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
+  __shared__ double red[kThreads / 64];
+  const CaseDesc* cs = cases + blockIdx.y;
+  const double* part = cs->d.err_part;
+  (void)0;
+  const int count = cs->n_err_part;
   double s = 0.0;
   for (int i = threadIdx.x; i < count; i += kThreads) s += part[i];
   s = block_sum_d(s, red);
-  if (threadIdx.x == 0) *out = (float)(s * inv_denom);
+  if (threadIdx.x == 0) cs->err_out[*it_ptr] = (float)(s * cs->inv_denom);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,7 +901,7 @@ __global__ __launch_bounds__(kThreads) void k_err_reduce(const double* __restric
 
 __global__ __launch_bounds__(kThreads) void k_prepare_amp(const float* __restrict__ inten, float* amp, int n,
                                                           int shift, int* bad, double* sum_part) {
-  __shared__ double red[kThreads];
+  __shared__ double red[kThreads / 64];
   const int pat = blockIdx.y;
   const size_t nn = (size_t)n * n;
   double s = 0.0;
@@ -853,149 +956,187 @@ bool supported_n(int n) {
   }
 }
 
-#define PTY_DISPATCH_N(n, MACRO) \
-  switch (n) {                   \
-    MACRO(8) MACRO(16) MACRO(24) MACRO(32) MACRO(48) MACRO(64) MACRO(96) MACRO(128) MACRO(192) MACRO(256) \
-    MACRO(384) MACRO(512) MACRO(768) MACRO(1024) default : return hipErrorInvalidValue; \
+#define PTY_FOR_EACH_N(MACRO) \
+  MACRO(8) MACRO(16) MACRO(24) MACRO(32) MACRO(48) MACRO(64) MACRO(96) MACRO(128) MACRO(192) MACRO(256) \
+  MACRO(384) MACRO(512) MACRO(768) MACRO(1024)
+
+template <int N>
+static int col_width_t(int v) {
+  switch (v) {
+    case 0: return ColW<N, 0>::C;
+    case 2: return ColW<N, 2>::C;
+    default: return ColW<N, 1>::C;
   }
+}
+template <int N>
+static bool col_valid_t(int v) {
+  return v == 1 || (v == 0 && ColW<N, 0>::VALID) || (v == 2 && ColW<N, 2>::VALID);
+}
+
+int col_width(int n, int v) {
+  switch (n) {
+#define PTY_CASE(N) \
+  case N:           \
+    return col_width_t<N>(v);
+    PTY_FOR_EACH_N(PTY_CASE)
+#undef PTY_CASE
+    default:
+      return 1;
+  }
+}
+bool col_variant_valid(int n, int v) {
+  switch (n) {
+#define PTY_CASE(N) \
+  case N:           \
+    return col_valid_t<N>(v);
+    PTY_FOR_EACH_N(PTY_CASE)
+#undef PTY_CASE
+    default:
+      return false;
+  }
+}
+int n_err_slots(int n, int v) { return n / col_width(n, v); }
+int max_err_slots(int n) {
+  int m = 0;
+  for (int v = 0; v < kColVariants; ++v)
+    if (col_variant_valid(n, v) && n_err_slots(n, v) > m) m = n_err_slots(n, v);
+  return m;
+}
+int n_obj_tiles(const DevParams& p) { return tiles_of(p); }
+int n_probe_blocks(int n) { return n_probe_blocks_dev(n); }
 
 template <int N, bool NEAR>
-static hipError_t fwd_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool with_v,
-                             hipStream_t s) {
+static hipError_t fwd_rows_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
   size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
   if (sh < sizeof(SideScratch)) sh = sizeof(SideScratch);
   const int gx = N / L;
-  const int jobs = n_obj_tiles(p) + (with_v ? n_probe_blocks(N) : 0);
-  const int side_rows = (jobs + gx - 1) / gx;
-  hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(gx, ns + side_rows), dim3(kThreads), sh, s, p, d, slots, ns,
-                     with_v ? 1 : 0);
+  const int side_rows = (t.max_side_jobs + gx - 1) / gx;
+  hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(gx * (t.max_batch + side_rows), t.n_cases), dim3(kThreads), sh, s,
+                     cases, beta, it);
   return hipGetLastError();
 }
 template <int N, bool NEAR>
-static hipError_t inv_rows_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                             const DebugPtrs& dbg, hipStream_t s) {
+static hipError_t inv_rows_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
-  hipLaunchKernelGGL((k_inv_rows<N, NEAR>), dim3(N / L, bmax), dim3(kThreads), sh, s, p, d, slots, ns, dbg);
+  hipLaunchKernelGGL((k_inv_rows<N, NEAR>), dim3((N / L) * t.max_batch, t.n_cases), dim3(kThreads), sh, s, cases,
+                     beta, it);
   return hipGetLastError();
 }
-template <int N, bool NEAR>
-static hipError_t fwd_cols_t(const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s) {
-  constexpr int C = Cfg<N>::COLS;
+template <int N, bool NEAR, int V>
+static hipError_t fwd_cols_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  constexpr int C = ColW<N, V>::C;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, C, true>::ELEMS);
-  hipLaunchKernelGGL((k_fwd_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, ns);
+  hipLaunchKernelGGL((k_fwd_cols<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
+                     cases, beta, it);
   return hipGetLastError();
+}
+template <int N, bool NEAR, int V>
+static hipError_t inv_cols_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  constexpr int C = ColW<N, V>::C;
+  const size_t fft = sizeof(float2) * Frame<N, C, true>::ELEMS;
+  const size_t halo = sizeof(float) * (size_t)N * (C + 2 * kMaxHalf);
+  const size_t sh = sizeof(float2) * 2 * N + (fft > halo ? fft : halo);
+  hipLaunchKernelGGL((k_inv_cols<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
+                     cases, beta, it);
+  return hipGetLastError();
+}
+// Column variants are instantiated for the frame sizes the autotuner explores.
+template <int N>
+struct TunedCols {
+  static constexpr bool value = N == 64 || N == 128 || N == 192 || N == 256 || N == 512;
+};
+template <int N, bool NEAR>
+static hipError_t fwd_cols_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  if constexpr (TunedCols<N>::value) {
+    if (t.col_variant == 0) return fwd_cols_v<N, NEAR, 0>(cases, t, beta, it, s);
+    if (t.col_variant == 2) return fwd_cols_v<N, NEAR, 2>(cases, t, beta, it, s);
+  }
+  return fwd_cols_v<N, NEAR, 1>(cases, t, beta, it, s);
 }
 template <int N, bool NEAR>
-static hipError_t inv_cols_t(const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                             const DebugPtrs& dbg, hipStream_t s) {
-  constexpr int C = Cfg<N>::COLS;
-  const size_t fft = sizeof(float2) * Frame<N, C, true>::ELEMS;
-  const size_t halo = sizeof(float) * (size_t)N * (C + 2 * p.ks_half);
-  const size_t sh = sizeof(float2) * 2 * N + (fft > halo ? fft : halo);
-  hipLaunchKernelGGL((k_inv_cols<N, NEAR>), dim3(N / C, bmax), dim3(kThreads), sh, s, p, d, slots, ns, dbg);
-  return hipGetLastError();
-}
-template <int N>
-static int cols_t() {
-  return Cfg<N>::COLS;
-}
-
-hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           bool with_v, hipStream_t s) {
-#define PTY_CASE(N) \
-  case N:           \
-    return near ? fwd_rows_t<N, true>(p, d, slots, ns, with_v, s) : fwd_rows_t<N, false>(p, d, slots, ns, with_v, s);
-  PTY_DISPATCH_N(n, PTY_CASE)
-#undef PTY_CASE
-}
-hipError_t launch_inv_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           int bmax, const DebugPtrs& dbg, hipStream_t s) {
-#define PTY_CASE(N)                                                  \
-  case N:                                                            \
-    return near ? inv_rows_t<N, true>(p, d, slots, ns, bmax, dbg, s) \
-                : inv_rows_t<N, false>(p, d, slots, ns, bmax, dbg, s);
-  PTY_DISPATCH_N(n, PTY_CASE)
-#undef PTY_CASE
-}
-hipError_t launch_fwd_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax,
-                           hipStream_t s) {
-#define PTY_CASE(N) \
-  case N:           \
-    return near ? fwd_cols_t<N, true>(p, d, ns, bmax, s) : fwd_cols_t<N, false>(p, d, ns, bmax, s);
-  PTY_DISPATCH_N(n, PTY_CASE)
-#undef PTY_CASE
-}
-hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           int bmax, const DebugPtrs& dbg, hipStream_t s) {
-#define PTY_CASE(N)                                                  \
-  case N:                                                            \
-    return near ? inv_cols_t<N, true>(p, d, slots, ns, bmax, dbg, s) \
-                : inv_cols_t<N, false>(p, d, slots, ns, bmax, dbg, s);
-  PTY_DISPATCH_N(n, PTY_CASE)
-#undef PTY_CASE
-}
-
-int n_err_slots(int n) {
-#define PTY_CASE(N) \
-  case N:           \
-    return N / cols_t<N>();
-  switch (n) {
-    PTY_CASE(8) PTY_CASE(16) PTY_CASE(24) PTY_CASE(32) PTY_CASE(48) PTY_CASE(64) PTY_CASE(96) PTY_CASE(128)
-    PTY_CASE(192) PTY_CASE(256) PTY_CASE(384) PTY_CASE(512) PTY_CASE(768) PTY_CASE(1024) default : return 0;
+static hipError_t inv_cols_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  if constexpr (TunedCols<N>::value) {
+    if (t.col_variant == 0) return inv_cols_v<N, NEAR, 0>(cases, t, beta, it, s);
+    if (t.col_variant == 2) return inv_cols_v<N, NEAR, 2>(cases, t, beta, it, s);
   }
-#undef PTY_CASE
+  return inv_cols_v<N, NEAR, 1>(cases, t, beta, it, s);
 }
-int n_obj_tiles(const DevParams& p) {
-  return ((p.h_obj + kObjTile - 1) / kObjTile) * ((p.w_obj + kObjTile - 1) / kObjTile);
-}
-int n_probe_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
 
-static dim3 obj_grid(const DevParams& p) {
-  return dim3((p.w_obj + kObjTile - 1) / kObjTile, (p.h_obj + kObjTile - 1) / kObjTile);
-}
-hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool cc_sums,
-                             const DebugPtrs& dbg, hipStream_t s) {
-  hipLaunchKernelGGL(k_obj_update, obj_grid(p), dim3(kThreads), 0, s, p, d, slots, ns, cc_sums ? 1 : 0, dbg);
+#define PTY_DEFINE_LAUNCH(FN)                                                                                  \
+  hipError_t launch_##FN(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {      \
+    switch (t.n) {                                                                                           \
+      PTY_FOR_EACH_N(PTY_CASE_##FN)                                                                          \
+      default:                                                                                               \
+        return hipErrorInvalidValue;                                                                         \
+    }                                                                                                        \
+  }
+#define PTY_CASE_fwd_rows(N) \
+  case N:                    \
+    return t.near_field ? fwd_rows_t<N, true>(cases, t, beta, it, s) : fwd_rows_t<N, false>(cases, t, beta, it, s);
+#define PTY_CASE_inv_rows(N) \
+  case N:                    \
+    return t.near_field ? inv_rows_t<N, true>(cases, t, beta, it, s) : inv_rows_t<N, false>(cases, t, beta, it, s);
+#define PTY_CASE_fwd_cols(N) \
+  case N:                    \
+    return t.near_field ? fwd_cols_t<N, true>(cases, t, beta, it, s) : fwd_cols_t<N, false>(cases, t, beta, it, s);
+#define PTY_CASE_inv_cols(N) \
+  case N:                    \
+    return t.near_field ? inv_cols_t<N, true>(cases, t, beta, it, s) : inv_cols_t<N, false>(cases, t, beta, it, s);
+PTY_DEFINE_LAUNCH(fwd_rows)
+PTY_DEFINE_LAUNCH(inv_rows)
+PTY_DEFINE_LAUNCH(fwd_cols)
+PTY_DEFINE_LAUNCH(inv_cols)
+
+hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_update, dim3(t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
 }
-hipError_t launch_post(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool probe, bool cc,
-                       hipStream_t s) {
-  int kp = 1;
-  while (kp < p.k) kp <<= 1;
-  const int px_per = kThreads / kp;
-  const int pb = probe ? (p.n * p.n + px_per - 1) / px_per : 0;
-  const int tiles = cc ? n_obj_tiles(p) : 0;
-  if (pb + tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_post, dim3(pb + tiles), dim3(kThreads), 0, s, p, d, slots, ns, pb, kp, tiles);
+hipError_t launch_post(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  const int pb = post_probe_blocks(t.n, t.max_k);
+  hipLaunchKernelGGL(k_post, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  return hipGetLastError();
+}
+hipError_t launch_gram(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
+  const int pairs = t.max_k * (t.max_k + 1) / 2;
+  hipLaunchKernelGGL(k_gram, dim3(kGramBlocks * pairs, t.n_cases), dim3(kThreads), 0, s, cases, it);
+  return hipGetLastError();
+}
+hipError_t launch_eig(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig, dim3(1, t.n_cases), dim3(64), 0, s, cases, it);
+  return hipGetLastError();
+}
+hipError_t launch_remix(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_remix, dim3(n_probe_blocks(t.n), t.n_cases), dim3(kThreads), 0, s, cases, it);
+  return hipGetLastError();
+}
+hipError_t launch_err_reduce(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_err_reduce, dim3(1, t.n_cases), dim3(kThreads), 0, s, cases, it);
   return hipGetLastError();
 }
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
   return hipGetLastError();
 }
-hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s) {
-  const int pairs = p.k * (p.k + 1) / 2;
-  hipLaunchKernelGGL(k_gram, dim3(kGramBlocks, pairs), dim3(kThreads), 0, s, p, d);
-  return hipGetLastError();
-}
-hipError_t launch_eig(const DevParams& p, const DevBufs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig, dim3(1), dim3(64), 0, s, p, d);
-  return hipGetLastError();
-}
-hipError_t launch_remix(const DevParams& p, const DevBufs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_remix, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
-  return hipGetLastError();
-}
-hipError_t launch_err_reduce(const double* part, int count, double inv_denom, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(kThreads), 0, s, part, count, inv_denom, out);
-  return hipGetLastError();
-}
 hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, bool shift, int* bad,
                               double* sum_part, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare_amp, dim3(8, n_pos), dim3(kThreads), 0, s, inten, amp, n, shift ? 1 : 0, bad,
                      sum_part);
+  return hipGetLastError();
+}
+__global__ void k_iter_advance(int* it) {
+  if (threadIdx.x == 0) *it = *it + 1;
+}
+__global__ void k_iter_set(int* it, int v) {
+  if (threadIdx.x == 0) *it = v;
+}
+hipError_t launch_iter_advance(int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, it);
+  return hipGetLastError();
+}
+hipError_t launch_iter_set(int* it, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_set, dim3(1), dim3(64), 0, s, it, v);
   return hipGetLastError();
 }
 hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* slots, int ns, float2* out,

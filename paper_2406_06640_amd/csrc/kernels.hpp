@@ -1,7 +1,16 @@
-// Device-side parameter/buffer structs and host launchers of the pc-ePIE kernels.
+// Device-side descriptors and host launchers of the pc-ePIE kernels.
+//
+// Every batch kernel reads its reconstruction ("case") from a device table of
+// CaseDesc: blockIdx.y selects the case, blockIdx.x the block within that
+// case's grid.  A single reconstruction is a table of one; a group of
+// independent reconstructions with the same frame size and geometry shares
+// each launch (cases whose batch index is past their last batch, or whose
+// grid is smaller, return at once).  A case's arithmetic does not depend on
+// the other cases in the table, so grouped and single runs agree bitwise.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace pty {
@@ -11,6 +20,10 @@ constexpr int kMaxModes = 16;
 constexpr int kMaxBatch = 256;
 constexpr int kObjTile = 32;     // object tile side for the gather/update kernels
 constexpr int kGramBlocks = 16;  // pixel chunks of the Gram matrix reduction
+constexpr int kColVariants = 3;  // column-tile widths tried by the autotuner: COLS/2, COLS, 2 COLS
+
+// Per-iteration flags of a case.
+enum : int { FLAG_PROBE = 1, FLAG_CC = 2, FLAG_ORTHO = 4 };
 
 struct DevParams {
   int n, k, h_obj, w_obj, n_pos;
@@ -25,25 +38,25 @@ struct DevParams {
 };
 
 struct DevBufs {
-  float2* obj;        // [H][W]
-  float2* probe;      // [K][N][N]
-  float* pw;          // [N][N] sum_k |P_k|^2
-  const float* amp;   // [n_pos][N][N] sqrt(max(I,0)) in detector pixel order
-  const int2* pos;    // [n_pos] (row, col)
-  const float2* tw;   // [N] exp(-2 pi i m / N)
-  const float2* hnear;// [N] near-field 1D transfer function, exp(-i pi u~^2/(N^2 F_px))
-  float2* X;          // [B][K][N][N] batch work frames
-  float* q;           // [B][N][N] vertically blurred sqrt(sum_k |Psi_k|^2) (or of the intensity)
-  float2* dO;         // [B][N][N] per-slot object numerator sum_k conj(P_k) dpsi_k
-  float2* nP;         // [K][N][N] probe numerator
-  float* V;           // [N][N] probe weight sum_b |o_b|^2
-  float* maxv_part;   // per-block max of V (one per 256 probe pixels)
-  float* maxw_part;   // per-object-tile max of W
-  double* err_part;   // [n_pos][column blocks per frame] data-error partial sums
-  double2* cc_part;   // [object tiles] (sum |ln A|, sum |phi|) weighted by box multiplicity
-  double2* gram_part; // [pairs][kGramBlocks]
-  float2* vmix;       // [K][K] eigenvectors (column j = mode j), float
-  double* eig;        // [K] eigenvalues
+  float2* obj;         // [H][W]
+  float2* probe;       // [K][N][N]
+  float* pw;           // [N][N] sum_k |P_k|^2
+  const float* amp;    // [n_pos][N][N] sqrt(max(I,0)) in detector pixel order
+  const int2* pos;     // [n_pos] (row, col)
+  const float2* tw;    // [N] exp(-2 pi i m / N)
+  const float2* hnear; // [N] near-field 1D transfer function, exp(-i pi u~^2/(N^2 F_px))
+  float2* X;           // [B][K][N][N] batch work frames
+  float* q;            // [B][N][N] vertically blurred sqrt(sum_k |Psi_k|^2) (or of the intensity)
+  float2* dO;          // [B][N][N] per-slot object numerator sum_k conj(P_k) dpsi_k
+  float2* nP;          // [K][N][N] probe numerator
+  float* V;            // [N][N] probe weight sum_b |o_b|^2
+  float* maxv_part;    // per-block max of V (one per 256 probe pixels)
+  float* maxw_part;    // per-object-tile max of W
+  double* err_part;    // [n_pos][column blocks per frame] data-error partial sums
+  double2* cc_part;    // [object tiles] (sum |ln A|, sum |phi|) weighted by box multiplicity
+  double2* gram_part;  // [pairs][kGramBlocks]
+  float2* vmix;        // [K][K] eigenvectors (column j = mode j), float
+  double* eig;         // [K] eigenvalues
 };
 
 struct DebugPtrs {
@@ -53,6 +66,29 @@ struct DebugPtrs {
   float* factor;    // [B][N][N] or null
 };
 
+struct CaseDesc {
+  DevParams p;
+  DevBufs d;
+  DebugPtrs dbg;
+  const int* order;  // [iterations of the call][n_pos] visiting order
+  const int* flags;  // [iterations of the call] FLAG_* bits
+  float* err_out;    // [iterations of the call] data error E_t
+  double inv_denom;  // 1 / sum_n sum_q I_n
+  int n_pos, batch, n_batches, n_err_part;
+};
+
+// Host-side launch geometry of one table of cases (all with the same n and geometry).
+struct TableShape {
+  int n;
+  bool near_field;
+  int n_cases;
+  int max_batch;       // max over cases of the batch size
+  int max_tiles;       // max over cases of object tiles
+  int max_k;           // max over cases of the number of modes
+  int max_side_jobs;   // max over cases of object tiles + V blocks
+  int col_variant;     // 0..kColVariants-1
+};
+
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_POST, KC_GRAM, KC_EIG, KC_REMIX,
@@ -60,23 +96,24 @@ enum KernelClass {
 };
 extern const char* const kKernelNames[KC_COUNT];
 
-// Launchers.  Each returns the hipGetLastError() after the launch.
-hipError_t launch_fwd_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           bool with_v, hipStream_t s);
-hipError_t launch_fwd_cols(int n, bool near, const DevParams& p, const DevBufs& d, int ns, int bmax, hipStream_t s);
-hipError_t launch_inv_cols(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns, int bmax,
-                           const DebugPtrs& dbg, hipStream_t s);
-hipError_t launch_inv_rows(int n, bool near, const DevParams& p, const DevBufs& d, const int* slots, int ns,
-                           int bmax, const DebugPtrs& dbg, hipStream_t s);
-hipError_t launch_obj_update(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool cc_sums,
-                             const DebugPtrs& dbg, hipStream_t s);
-hipError_t launch_post(const DevParams& p, const DevBufs& d, const int* slots, int ns, bool probe, bool cc,
-                       hipStream_t s);
-hipError_t launch_gram(const DevParams& p, const DevBufs& d, hipStream_t s);
-hipError_t launch_eig(const DevParams& p, const DevBufs& d, hipStream_t s);
-hipError_t launch_remix(const DevParams& p, const DevBufs& d, hipStream_t s);
-hipError_t launch_err_reduce(const double* part, int count, double inv_denom, float* out, hipStream_t s);
-// init-time helpers
+// Batch launches for batch index `beta` of the call's current iteration, which
+// the kernels read from the device counter `it` (so that a captured iteration
+// graph can be replayed unchanged).
+hipError_t launch_fwd_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_fwd_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_inv_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_inv_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_post(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+// Per-iteration launches.
+hipError_t launch_gram(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
+hipError_t launch_eig(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
+hipError_t launch_remix(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
+hipError_t launch_err_reduce(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
+// The iteration counter: advance by one / set.
+hipError_t launch_iter_advance(int* it, hipStream_t s);
+hipError_t launch_iter_set(int* it, int v, hipStream_t s);
+// Init-time and debug helpers (one case, parameters by value).
 hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, bool shift, int* bad_count,
                               double* sum_part, hipStream_t s);
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s);
@@ -84,8 +121,11 @@ hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* sl
                              hipStream_t s);
 
 int n_obj_tiles(const DevParams& p);
-int n_err_slots(int n);  // data-error partials per position (one per column block)
+int n_err_slots(int n, int col_variant);  // data-error partials per position (one per column block)
+int max_err_slots(int n);                 // over all column variants
 int n_probe_blocks(int n);
+int col_width(int n, int col_variant);    // columns per column block
+bool col_variant_valid(int n, int col_variant);
 bool supported_n(int n);
 
 }  // namespace pty

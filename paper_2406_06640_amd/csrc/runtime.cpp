@@ -1,12 +1,20 @@
 // Host runtime of the pc-ePIE library: validation, device memory, the iteration
-// schedule and the C ABI declared in include/ptycho.h.
+// schedule (eager or replayed from a captured HIP graph), groups of
+// independent reconstructions, the column-tile autotuner, and the C ABI
+// declared in include/ptycho.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ptycho.h"
@@ -27,6 +35,18 @@ struct Timing {
   size_t used = 0;
 };
 
+// Device and pinned host buffers of one call's schedule (orders, flags, errors).
+struct CallBufs {
+  int* d_order = nullptr;
+  int* h_order = nullptr;
+  size_t order_cap = 0;
+  int* d_flags = nullptr;
+  int* h_flags = nullptr;
+  float* d_err = nullptr;
+  float* h_err = nullptr;
+  size_t iter_cap = 0;
+};
+
 }  // namespace
 
 struct ptycho_ctx {
@@ -39,16 +59,39 @@ struct ptycho_ctx {
   bool failed = false;
   std::string err;
   double inv_denom = 0.0;  // 1 / sum_n sum_q I_n
-  // owned device allocations
   std::vector<void*> allocs;
-  int* d_order = nullptr;   // [order_cap]
-  size_t order_cap = 0;
-  int* h_order = nullptr;   // pinned staging
-  float* d_err = nullptr;   // [err_cap]
-  size_t err_cap = 0;
-  int bmax = 1;
-  int n_err_part = 0;
+  CallBufs call;
+  int* d_iter = nullptr;           // device iteration counter of the current call
+  CaseDesc* h_case = nullptr;      // pinned staging of the case table (one entry)
+  CaseDesc* d_case = nullptr;
+  CaseDesc* d_case_dbg = nullptr;  // table used by ptycho_debug_step
+  int* d_dbg_order = nullptr;      // [batch]
+  int* d_dbg_flags = nullptr;      // [1]
+  int* d_dbg_iter = nullptr;
+  float* d_dbg_err = nullptr;
+  int col_variant = 1;
+  // graph replay of one iteration
+  bool use_graph = false;
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   Timing tm;
+};
+
+struct ptycho_group {
+  std::vector<ptycho_ctx*> ctx;
+  struct Table {
+    TableShape shape{};
+    std::vector<int> members;  // indices into ctx
+    CaseDesc* d_cases = nullptr;
+    CaseDesc* h_cases = nullptr;  // pinned
+  };
+  std::vector<Table> tables;
+  hipStream_t stream = nullptr;
+  CallBufs call;
+  int* d_iter = nullptr;
+  std::vector<void*> allocs;
+  std::string err;
 };
 
 namespace {
@@ -58,12 +101,23 @@ ptycho_status fail(ptycho_ctx* c, ptycho_status st, const std::string& msg) {
   else g_thread_error = msg;
   return st;
 }
+ptycho_status gfail(ptycho_group* g, ptycho_status st, const std::string& msg) {
+  if (g) g->err = msg;
+  else g_thread_error = msg;
+  return st;
+}
 
 #define HIP_TRY(ctx, expr)                                                              \
   do {                                                                                  \
     hipError_t e_ = (expr);                                                             \
     if (e_ != hipSuccess)                                                               \
       return fail((ctx), PTYCHO_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define HIP_GTRY(g, expr)                                                                \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return gfail((g), PTYCHO_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
 bool finite_f(float v) { return std::isfinite(v); }
@@ -129,13 +183,68 @@ ptycho_status dev_alloc(ptycho_ctx* c, T** ptr, size_t count) {
 hipMemcpyKind kind_in(int32_t mem_kind) { return mem_kind == PTYCHO_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
 hipMemcpyKind kind_out(int32_t mem_kind) { return mem_kind == PTYCHO_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
 
+
+template <typename T>
+void drop_alloc(std::vector<void*>& allocs, T*& ptr) {
+  if (!ptr) return;
+  (void)hipFree(ptr);
+  auto it = std::find(allocs.begin(), allocs.end(), (void*)ptr);
+  if (it != allocs.end()) allocs.erase(it);
+  ptr = nullptr;
+}
+
+// Grow the schedule buffers to orders for `n_order` ints and `n_iter` iterations.
+template <class Owner>
+bool grow_call(Owner* o, std::vector<void*>& allocs, CallBufs& cb, size_t n_order, size_t n_iter) {
+  if (n_order > cb.order_cap) {
+    drop_alloc(allocs, cb.d_order);
+    if (cb.h_order) (void)hipHostFree(cb.h_order);
+    cb.h_order = nullptr;
+    cb.order_cap = 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, n_order * sizeof(int)) != hipSuccess) return false;
+    allocs.push_back(p);
+    cb.d_order = (int*)p;
+    if (hipHostMalloc((void**)&cb.h_order, n_order * sizeof(int), hipHostMallocDefault) != hipSuccess) return false;
+    cb.order_cap = n_order;
+  }
+  if (n_iter > cb.iter_cap) {
+    drop_alloc(allocs, cb.d_flags);
+    drop_alloc(allocs, cb.d_err);
+    if (cb.h_flags) (void)hipHostFree(cb.h_flags);
+    if (cb.h_err) (void)hipHostFree(cb.h_err);
+    cb.h_flags = nullptr;
+    cb.h_err = nullptr;
+    cb.iter_cap = 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, n_iter * sizeof(int)) != hipSuccess) return false;
+    allocs.push_back(p);
+    cb.d_flags = (int*)p;
+    if (hipMalloc(&p, n_iter * sizeof(float)) != hipSuccess) return false;
+    allocs.push_back(p);
+    cb.d_err = (float*)p;
+    if (hipHostMalloc((void**)&cb.h_flags, n_iter * sizeof(int), hipHostMallocDefault) != hipSuccess) return false;
+    if (hipHostMalloc((void**)&cb.h_err, n_iter * sizeof(float), hipHostMallocDefault) != hipSuccess) return false;
+    cb.iter_cap = n_iter;
+  }
+  (void)o;
+  return true;
+}
+
+void free_call(CallBufs& cb) {
+  if (cb.h_order) (void)hipHostFree(cb.h_order);
+  if (cb.h_flags) (void)hipHostFree(cb.h_flags);
+  if (cb.h_err) (void)hipHostFree(cb.h_err);
+  cb = CallBufs{};
+}
+
 // Time one launch of class `cls` if selected.
 struct Timed {
   ptycho_ctx* c;
-  int cls;
+  hipStream_t s;
   hipEvent_t stop = nullptr;
-  Timed(ptycho_ctx* ctx, int k) : c(ctx), cls(k) {
-    if (!(c->tm.mask & (1u << k))) return;
+  Timed(ptycho_ctx* ctx, int k, hipStream_t st) : c(ctx), s(st) {
+    if (!c || !(c->tm.mask & (1u << k))) return;
     if (c->tm.used * 2 + 2 > c->tm.pool.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t e;
@@ -148,10 +257,10 @@ struct Timed {
     c->tm.cls.resize(c->tm.used + 1);
     c->tm.cls[c->tm.used] = k;
     c->tm.used++;
-    (void)hipEventRecord(start, c->stream);
+    (void)hipEventRecord(start, s);
   }
   ~Timed() {
-    if (stop) (void)hipEventRecord(stop, c->stream);
+    if (stop) (void)hipEventRecord(stop, s);
   }
 };
 
@@ -166,44 +275,38 @@ void harvest_timing(ptycho_ctx* c) {
   c->tm.used = 0;
 }
 
-#define LAUNCH(ctx, cls, expr)                                                            \
-  do {                                                                                    \
-    hipError_t e_;                                                                        \
-    {                                                                                     \
-      Timed tmd_((ctx), (cls));                                                           \
-      e_ = (expr);                                                                        \
-    }                                                                                     \
-    if (e_ != hipSuccess)                                                                 \
-      return fail((ctx), PTYCHO_E_HIP, std::string(kKernelNames[cls]) + ": " + hipGetErrorString(e_)); \
+// Launch `expr`; on failure return the HIP error text.  `tc` (may be null) times it.
+#define LAUNCH(tc, cls, s, expr)                                                           \
+  do {                                                                                     \
+    hipError_t e_;                                                                         \
+    {                                                                                      \
+      Timed tmd_((tc), (cls), (s));                                                        \
+      e_ = (expr);                                                                         \
+    }                                                                                      \
+    if (e_ != hipSuccess) return std::string(kKernelNames[cls]) + ": " + hipGetErrorString(e_); \
   } while (0)
 
-// One batch update: the body of Fig. 1 over slots[0..ns).
-ptycho_status run_batch(ptycho_ctx* c, const int* d_slots, int ns, int t, const DebugPtrs& dbg) {
-  const DevParams& p = c->dp;
-  const DevBufs& d = c->db;
-  const bool near = c->prm.geometry == PTYCHO_NEAR_FIELD;
-  hipStream_t s = c->stream;
-  const int bm = ns;  // grid sized to the batch
-  const bool cc = in_window(c->prm, t);
-  const bool probe = t >= c->prm.probe_update_start;
-  LAUNCH(c, KC_FWD_ROWS, launch_fwd_rows(p.n, near, p, d, d_slots, ns, probe, s));
-  LAUNCH(c, KC_FWD_COLS, launch_fwd_cols(p.n, near, p, d, ns, bm, s));
-  LAUNCH(c, KC_INV_COLS, launch_inv_cols(p.n, near, p, d, d_slots, ns, bm, dbg, s));
-  LAUNCH(c, KC_INV_ROWS, launch_inv_rows(p.n, near, p, d, d_slots, ns, bm, dbg, s));
-  LAUNCH(c, KC_OBJ_UPDATE, launch_obj_update(p, d, d_slots, ns, cc, dbg, s));
-  if (probe || cc) LAUNCH(c, KC_POST, launch_post(p, d, d_slots, ns, probe, cc, s));
-  return PTYCHO_OK;
+// The six launches of batch `beta` for every case of a table.
+std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
+                         hipStream_t s) {
+  LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_FWD_COLS, s, launch_fwd_cols(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_INV_COLS, s, launch_inv_cols(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_INV_ROWS, s, launch_inv_rows(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_POST, s, launch_post(cases, sh, beta, it, s));
+  return "";
 }
 
-ptycho_status end_iteration(ptycho_ctx* c, float* d_err_slot) {
-  const DevParams& p = c->dp;
-  if (p.k > 1 && c->prm.orthogonalize) {
-    LAUNCH(c, KC_GRAM, launch_gram(p, c->db, c->stream));
-    LAUNCH(c, KC_EIG, launch_eig(p, c->db, c->stream));
-    LAUNCH(c, KC_REMIX, launch_remix(p, c->db, c->stream));
+// Mode orthogonalisation (cases flagged) and the data error of every case.
+std::string launch_end(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, const int* it, hipStream_t s) {
+  if (sh.max_k > 1) {
+    LAUNCH(tc, KC_GRAM, s, launch_gram(cases, sh, it, s));
+    LAUNCH(tc, KC_EIG, s, launch_eig(cases, sh, it, s));
+    LAUNCH(tc, KC_REMIX, s, launch_remix(cases, sh, it, s));
   }
-  LAUNCH(c, KC_ERR, launch_err_reduce(c->db.err_part, c->n_err_part, c->inv_denom, d_err_slot, c->stream));
-  return PTYCHO_OK;
+  LAUNCH(tc, KC_ERR, s, launch_err_reduce(cases, sh, it, s));
+  return "";
 }
 
 void splitmix_perm(uint64_t seed, int32_t t, int32_t n, int32_t* out) {
@@ -220,35 +323,86 @@ void splitmix_perm(uint64_t seed, int32_t t, int32_t n, int32_t* out) {
   }
 }
 
-ptycho_status ensure_order_capacity(ptycho_ctx* c, size_t count) {
-  if (count <= c->order_cap) return PTYCHO_OK;
-  if (c->d_order) {
-    (void)hipFree(c->d_order);
-    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)c->d_order));
-    c->d_order = nullptr;
-  }
-  if (c->h_order) {
-    (void)hipHostFree(c->h_order);
-    c->h_order = nullptr;
-  }
-  ptycho_status st = dev_alloc(c, &c->d_order, count);
-  if (st != PTYCHO_OK) return st;
-  hipError_t e = hipHostMalloc((void**)&c->h_order, count * sizeof(int), hipHostMallocDefault);
-  if (e != hipSuccess) return fail(c, PTYCHO_E_OOM, "pinned host allocation failed");
-  c->order_cap = count;
-  return PTYCHO_OK;
+
+int case_flags(const ptycho_params& p, int t) {
+  int f = 0;
+  if (t >= p.probe_update_start) f |= FLAG_PROBE;
+  if (in_window(p, t)) f |= FLAG_CC;
+  if (p.n_modes > 1 && p.orthogonalize) f |= FLAG_ORTHO;
+  return f;
 }
 
-ptycho_status ensure_err_capacity(ptycho_ctx* c, size_t count) {
-  if (count <= c->err_cap) return PTYCHO_OK;
-  if (c->d_err) {
-    (void)hipFree(c->d_err);
-    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)c->d_err));
-    c->d_err = nullptr;
+int n_batches_of(const ptycho_params& p) { return (p.n_pos + p.batch - 1) / p.batch; }
+
+// Fill the per-case fields of a table entry for the current call.
+void fill_case(const ptycho_ctx* c, CaseDesc& cd, const int* order, const int* flags, float* err) {
+  cd.p = c->dp;
+  cd.d = c->db;
+  cd.dbg = DebugPtrs{nullptr, nullptr, nullptr, nullptr};
+  cd.order = order;
+  cd.flags = flags;
+  cd.err_out = err;
+  cd.inv_denom = c->inv_denom;
+  cd.n_pos = c->prm.n_pos;
+  cd.batch = c->prm.batch;
+  cd.n_batches = n_batches_of(c->prm);
+  cd.n_err_part = c->prm.n_pos * n_err_slots(c->prm.n, c->col_variant);
+}
+
+TableShape single_shape(const ptycho_ctx* c, int max_batch) {
+  TableShape sh{};
+  sh.n = c->prm.n;
+  sh.near_field = c->prm.geometry == PTYCHO_NEAR_FIELD;
+  sh.n_cases = 1;
+  sh.max_batch = max_batch;
+  sh.max_tiles = n_obj_tiles(c->dp);
+  sh.max_k = c->prm.n_modes;
+  sh.max_side_jobs = sh.max_tiles + n_probe_blocks(c->prm.n);
+  sh.col_variant = c->col_variant;
+  return sh;
+}
+
+// One iteration of a single context on stream s (eager or under capture).
+std::string enqueue_iteration(ptycho_ctx* c, hipStream_t s, bool timed) {
+  const TableShape sh = single_shape(c, c->prm.batch);
+  ptycho_ctx* tc = timed ? c : nullptr;
+  const int nb = n_batches_of(c->prm);
+  for (int beta = 0; beta < nb; ++beta) {
+    std::string e = launch_batch(tc, c->d_case, sh, beta, c->d_iter, s);
+    if (!e.empty()) return e;
   }
-  ptycho_status st = dev_alloc(c, &c->d_err, count);
-  if (st != PTYCHO_OK) return st;
-  c->err_cap = count;
+  std::string e = launch_end(tc, c->d_case, sh, c->d_iter, s);
+  if (!e.empty()) return e;
+  hipError_t he = launch_iter_advance(c->d_iter, s);
+  if (he != hipSuccess) return std::string("iter_advance: ") + hipGetErrorString(he);
+  return "";
+}
+
+void drop_graph(ptycho_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+}
+
+ptycho_status build_graph(ptycho_ctx* c) {
+  if (c->gexec) return PTYCHO_OK;
+  if (!c->gstream) HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+  if (!c->ev_in) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  if (!c->ev_out) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  HIP_TRY(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+  std::string e = enqueue_iteration(c, c->gstream, false);
+  hipGraph_t graph = nullptr;
+  hipError_t he = hipStreamEndCapture(c->gstream, &graph);
+  if (!e.empty()) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(c, PTYCHO_E_HIP, "capturing the iteration: " + e);
+  }
+  if (he != hipSuccess) return fail(c, PTYCHO_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+  he = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (he != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(c, PTYCHO_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+  }
   return PTYCHO_OK;
 }
 
@@ -270,6 +424,38 @@ ptycho_status fetch_host(ptycho_ctx* c, const float* src, size_t count, int32_t 
     std::memcpy(out.data(), src, count * sizeof(float));
   }
   return PTYCHO_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Column-tile autotuner: times each valid column-block width on the first
+// batch of a context, keeps the fastest; results are cached per
+// (n, K, batch, geometry) for the process, and in the file named by the
+// environment variable PTYCHO_TUNE_CACHE if it is set.
+// ---------------------------------------------------------------------------
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("PTYCHO_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  int n, k, b, g, v;
+  while (f >> n >> k >> b >> g >> v)
+    if (v >= 0 && v < kColVariants) g_tune[std::make_tuple(n, k, b, g)] = v;
+}
+
+void tune_store_locked(const std::tuple<int, int, int, int>& key, int v) {
+  g_tune[key] = v;
+  const char* path = std::getenv("PTYCHO_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' ' << v
+    << '\n';
 }
 
 }  // namespace
@@ -301,6 +487,7 @@ void ptycho_default_params(ptycho_params* p) {
   p->orthogonalize = 1;
   p->seed = 0;
 }
+
 
 ptycho_status ptycho_permutation(uint64_t seed, int32_t t, int32_t n_pos, int32_t* out) {
   if (n_pos < 0 || (n_pos > 0 && !out)) return fail(nullptr, PTYCHO_E_INVALID, "bad permutation arguments");
@@ -394,7 +581,6 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   gaussian_taps(p.sigma2, dp.ks_half, dp.gy);
 
   const int B = p.batch;
-  c->bmax = B;
   DevBufs& d = c->db;
   float2 *obj, *probe, *tw, *hn, *X, *dO, *nP, *vmix;
   float *pw, *amp, *q, *V, *maxv, *maxw;
@@ -402,19 +588,28 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   double *errp, *eig;
   double2 *ccp, *gramp;
   const int nobjt = n_obj_tiles(dp);
-  const int nbt = n_err_slots(n);
+  const int nbt = max_err_slots(n);
   ptycho_status st = PTYCHO_OK;
   if ((st = dev_alloc(c, &obj, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &probe, K * nn)) ||
       (st = dev_alloc(c, &pw, nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
       (st = dev_alloc(c, &pos, (size_t)p.n_pos)) || (st = dev_alloc(c, &tw, (size_t)n)) ||
       (st = dev_alloc(c, &hn, (size_t)n)) || (st = dev_alloc(c, &X, (size_t)B * K * nn)) ||
-      (st = dev_alloc(c, &q, (size_t)B * nn)) ||
-      (st = dev_alloc(c, &dO, (size_t)B * nn)) || (st = dev_alloc(c, &nP, K * nn)) || (st = dev_alloc(c, &V, nn)) ||
+      (st = dev_alloc(c, &q, (size_t)B * nn)) || (st = dev_alloc(c, &dO, (size_t)B * nn)) ||
+      (st = dev_alloc(c, &nP, K * nn)) || (st = dev_alloc(c, &V, nn)) ||
       (st = dev_alloc(c, &maxv, (size_t)n_probe_blocks(n))) || (st = dev_alloc(c, &maxw, (size_t)nobjt)) ||
       (st = dev_alloc(c, &errp, (size_t)p.n_pos * nbt)) || (st = dev_alloc(c, &ccp, (size_t)nobjt)) ||
-      (st = dev_alloc(c, &gramp, (size_t)(K * (K + 1) / 2) * kGramBlocks)) || (st = dev_alloc(c, &vmix, (size_t)K * K)) ||
-      (st = dev_alloc(c, &eig, (size_t)K)))
+      (st = dev_alloc(c, &gramp, (size_t)(K * (K + 1) / 2) * kGramBlocks)) ||
+      (st = dev_alloc(c, &vmix, (size_t)K * K)) || (st = dev_alloc(c, &eig, (size_t)K)) ||
+      (st = dev_alloc(c, &c->d_iter, 1)) || (st = dev_alloc(c, &c->d_case, 1)) ||
+      (st = dev_alloc(c, &c->d_case_dbg, 1)) || (st = dev_alloc(c, &c->d_dbg_order, (size_t)B)) ||
+      (st = dev_alloc(c, &c->d_dbg_flags, 1)) || (st = dev_alloc(c, &c->d_dbg_iter, 1)) ||
+      (st = dev_alloc(c, &c->d_dbg_err, 1)))
     return bail(st);
+  if (hipHostMalloc((void**)&c->h_case, sizeof(CaseDesc), hipHostMallocDefault) != hipSuccess) {
+    c->h_case = nullptr;
+    c->err = "pinned host allocation failed";
+    return bail(PTYCHO_E_OOM);
+  }
   d.obj = obj;
   d.probe = probe;
   d.pw = pw;
@@ -434,7 +629,6 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   d.gram_part = gramp;
   d.vmix = vmix;
   d.eig = eig;
-  c->n_err_part = p.n_pos * nbt;
 
   // tables (double precision on the host)
   std::vector<float2> htw(n), hh(n);
@@ -484,15 +678,9 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   INIT_TRY(hipMemcpyAsync(hb.data(), d_bad, hb.size() * sizeof(int), hipMemcpyDeviceToHost, s));
   INIT_TRY(hipMemcpyAsync(hs.data(), d_sum, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   INIT_TRY(hipStreamSynchronize(s));
-  // free the init temporaries
-  auto drop = [&](void* ptr) {
-    if (!ptr) return;
-    (void)hipFree(ptr);
-    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), ptr));
-  };
-  if (mem_kind == PTYCHO_MEM_HOST) drop(raw);
-  drop(d_bad);
-  drop(d_sum);
+  if (mem_kind == PTYCHO_MEM_HOST) drop_alloc(c->allocs, raw);
+  drop_alloc(c->allocs, d_bad);
+  drop_alloc(c->allocs, d_sum);
   long long nbad = 0;
   double denom = 0.0;
   for (size_t i = 0; i < hb.size(); ++i) {
@@ -504,23 +692,24 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
     return bail(PTYCHO_E_INVALID);
   }
   c->inv_denom = denom > 0 ? 1.0 / denom : 0.0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(std::make_tuple(n, K, B, (int)p.geometry));
+    if (it != g_tune.end() && col_variant_valid(n, it->second)) c->col_variant = it->second;
+  }
   *out = c;
   return PTYCHO_OK;
 }
 
-ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order, float* err_out) {
-  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
-  if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
-  if (n_iter < 0) return fail(c, PTYCHO_E_INVALID, "n_iter must be >= 0");
-  if (n_iter == 0) return PTYCHO_OK;
+// Fill the schedule of n_iter iterations of context c into its call buffers.
+static ptycho_status stage_call(ptycho_ctx* c, int32_t n_iter, const int32_t* order) {
   const int np = c->prm.n_pos;
-  ptycho_status st = ensure_order_capacity(c, (size_t)n_iter * np);
-  if (st != PTYCHO_OK) return st;
-  if ((st = ensure_err_capacity(c, (size_t)n_iter)) != PTYCHO_OK) return st;
-  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the pinned staging buffer may be in use
+  if (!grow_call(c, c->allocs, c->call, (size_t)n_iter * np, (size_t)n_iter))
+    return fail(c, PTYCHO_E_OOM, "schedule buffer allocation failed");
   std::vector<char> seen(np);
   for (int it = 0; it < n_iter; ++it) {
-    int32_t* row = c->h_order + (size_t)it * np;
+    int32_t* row = c->call.h_order + (size_t)it * np;
     if (order) {
       std::memcpy(row, order + (size_t)it * np, np * sizeof(int32_t));
       std::fill(seen.begin(), seen.end(), 0);
@@ -532,31 +721,59 @@ ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order
     } else {
       splitmix_perm(c->prm.seed, c->t + 1 + it, np, row);
     }
+    c->call.h_flags[it] = case_flags(c->prm, c->t + 1 + it);
   }
-  HIP_TRY(c, hipMemcpyAsync(c->d_order, c->h_order, (size_t)n_iter * np * sizeof(int32_t), hipMemcpyHostToDevice,
-                            c->stream));
-  const int B = c->prm.batch;
-  DebugPtrs none{nullptr, nullptr, nullptr, nullptr};
-  for (int it = 0; it < n_iter; ++it) {
-    const int t = c->t + 1 + it;
-    const int* ord = c->d_order + (size_t)it * np;
-    for (int s0 = 0; s0 < np; s0 += B) {
-      st = run_batch(c, ord + s0, std::min(B, np - s0), t, none);
-      if (st != PTYCHO_OK) return st;
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order, float* err_out) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
+  if (n_iter < 0) return fail(c, PTYCHO_E_INVALID, "n_iter must be >= 0");
+  if (n_iter == 0) return PTYCHO_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the pinned staging buffers may still be in use
+  ptycho_status st = stage_call(c, n_iter, order);
+  if (st != PTYCHO_OK) return st;
+  const int np = c->prm.n_pos;
+  fill_case(c, *c->h_case, c->call.d_order, c->call.d_flags, c->call.d_err);
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipMemcpyAsync(c->call.d_order, c->call.h_order, (size_t)n_iter * np * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->call.d_flags, c->call.h_flags, n_iter * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->d_case, c->h_case, sizeof(CaseDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, launch_iter_set(c->d_iter, 0, s));
+  const bool timed = c->tm.mask != 0;
+  if (c->use_graph && !timed) {
+    if ((st = build_graph(c)) != PTYCHO_OK) return st;
+    HIP_TRY(c, hipEventRecord(c->ev_in, s));
+    HIP_TRY(c, hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+    for (int it = 0; it < n_iter; ++it) HIP_TRY(c, hipGraphLaunch(c->gexec, c->gstream));
+    HIP_TRY(c, hipEventRecord(c->ev_out, c->gstream));
+    HIP_TRY(c, hipStreamWaitEvent(s, c->ev_out, 0));
+  } else {
+    for (int it = 0; it < n_iter; ++it) {
+      std::string e = enqueue_iteration(c, s, timed);
+      if (!e.empty()) return fail(c, PTYCHO_E_HIP, e);
     }
-    if ((st = end_iteration(c, c->d_err + it)) != PTYCHO_OK) return st;
   }
-  std::vector<float> herr(n_iter);
-  HIP_TRY(c, hipMemcpyAsync(herr.data(), c->d_err, n_iter * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->call.h_err, c->call.d_err, n_iter * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
   if (c->tm.used) harvest_timing(c);
   c->t += n_iter;
-  if (err_out) std::memcpy(err_out, herr.data(), n_iter * sizeof(float));
+  if (err_out) std::memcpy(err_out, c->call.h_err, n_iter * sizeof(float));
   for (int i = 0; i < n_iter; ++i)
-    if (!std::isfinite(herr[i])) {
+    if (!std::isfinite(c->call.h_err[i])) {
       c->failed = true;
-      return fail(c, PTYCHO_E_NUMERIC, "non-finite data error at iteration " + std::to_string(c->t - n_iter + 1 + i));
+      return fail(c, PTYCHO_E_NUMERIC,
+                  "non-finite data error at iteration " + std::to_string(c->t - n_iter + 1 + i));
     }
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_set_graph(ptycho_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graph(c);
   return PTYCHO_OK;
 }
 
@@ -610,16 +827,10 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   if ((n_obj == nullptr) != (w_obj == nullptr)) return fail(c, PTYCHO_E_INVALID, "n_obj and w_obj go together");
   for (int i = 0; i < B; ++i)
     if (idx[i] < 0 || idx[i] >= c->prm.n_pos) return fail(c, PTYCHO_E_INVALID, "index out of range");
-  ptycho_status st = ensure_order_capacity(c, (size_t)std::max(B, c->prm.n_pos));
-  if (st != PTYCHO_OK) return st;
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memcpy(c->h_order, idx, B * sizeof(int32_t));
-  HIP_TRY(c, hipMemcpyAsync(c->d_order, c->h_order, B * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipStreamSynchronize(s));
   const int n = c->prm.n, K = c->prm.n_modes;
   const size_t nn = (size_t)n * n, no = (size_t)c->prm.obj_h * c->prm.obj_w;
-  // device staging for the captures
-  float2 *d_psi = nullptr, *d_psin = nullptr, *d_nobj = nullptr;
-  float* d_wobj = nullptr;
   std::vector<void*> tmp;
   auto alloc_tmp = [&](size_t bytes, void** p) -> bool {
     if (hipMalloc(p, bytes) != hipSuccess) return false;
@@ -629,55 +840,153 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   auto cleanup = [&]() {
     for (void* p : tmp) (void)hipFree(p);
   };
+  float2 *d_psi = nullptr, *d_psin = nullptr, *d_nobj = nullptr;
+  float *d_wobj = nullptr, *d_fac = nullptr;
   bool ok = true;
   if (psi) ok = ok && alloc_tmp((size_t)B * K * nn * sizeof(float2), (void**)&d_psi);
   if (psi_new) ok = ok && alloc_tmp((size_t)B * K * nn * sizeof(float2), (void**)&d_psin);
   if (n_obj) ok = ok && alloc_tmp(no * sizeof(float2), (void**)&d_nobj) && alloc_tmp(no * sizeof(float), (void**)&d_wobj);
+  if (factor) ok = ok && alloc_tmp((size_t)B * nn * sizeof(float), (void**)&d_fac);
   if (!ok) {
     cleanup();
     return fail(c, PTYCHO_E_OOM, "debug staging allocation failed");
   }
-  if (d_nobj) {
-    (void)hipMemsetAsync(d_nobj, 0, no * sizeof(float2), c->stream);
-    (void)hipMemsetAsync(d_wobj, 0, no * sizeof(float), c->stream);
-  }
-  if (n_probe) (void)hipMemsetAsync(c->db.nP, 0, K * nn * sizeof(float2), c->stream);
-  if (v_probe) (void)hipMemsetAsync(c->db.V, 0, nn * sizeof(float), c->stream);
-  if (d_psi) {
-    hipError_t e = launch_exit_waves(c->dp, c->db, c->d_order, B, d_psi, c->stream);
-    if (e != hipSuccess) {
-      cleanup();
-      return fail(c, PTYCHO_E_HIP, std::string("exit waves: ") + hipGetErrorString(e));
-    }
-  }
-  float* d_fac = nullptr;
-  if (factor && !alloc_tmp((size_t)B * nn * sizeof(float), (void**)&d_fac)) {
-    cleanup();
-    return fail(c, PTYCHO_E_OOM, "debug staging allocation failed");
-  }
-  DebugPtrs dbg{d_psin, d_nobj, d_wobj, d_fac};
-  st = run_batch(c, c->d_order, B, t, dbg);
-  auto copy = [&](float* dst, const void* src, size_t bytes) -> hipError_t {
-    return dst ? hipMemcpyAsync(dst, src, bytes, kind_out(mem_kind), c->stream) : hipSuccess;
-  };
+  // schedule of the one batch: order = idx, flags of iteration t
+  std::vector<int> hidx(idx, idx + B);
+  const int flags = case_flags(c->prm, t) & ~FLAG_ORTHO;
+  CaseDesc cd;
+  fill_case(c, cd, c->d_dbg_order, c->d_dbg_flags, c->d_dbg_err);
+  cd.dbg = DebugPtrs{d_psin, d_nobj, d_wobj, d_fac};
+  cd.n_pos = B;
+  cd.batch = B;
+  cd.n_batches = 1;
   hipError_t e = hipSuccess;
-  if (st == PTYCHO_OK) {
-    if (e == hipSuccess) e = copy(psi, d_psi, (size_t)B * K * nn * sizeof(float2));
-    if (e == hipSuccess) e = copy(psi_new, d_psin, (size_t)B * K * nn * sizeof(float2));
-    if (e == hipSuccess) e = copy(factor, d_fac, (size_t)B * nn * sizeof(float));
-    if (e == hipSuccess) e = copy(n_obj, d_nobj, no * sizeof(float2));
-    if (e == hipSuccess) e = copy(w_obj, d_wobj, no * sizeof(float));
-    if (e == hipSuccess) e = copy(n_probe, c->db.nP, K * nn * sizeof(float2));
-    if (e == hipSuccess) e = copy(v_probe, c->db.V, nn * sizeof(float));
-    hipError_t e2 = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = e2;
-  } else {
-    (void)hipStreamSynchronize(c->stream);
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chk(hipMemcpyAsync(c->d_dbg_order, hidx.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(c->d_dbg_flags, &flags, sizeof(int), hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(c->d_case_dbg, &cd, sizeof(CaseDesc), hipMemcpyHostToDevice, s));
+  chk(launch_iter_set(c->d_dbg_iter, 0, s));
+  if (d_nobj) {
+    chk(hipMemsetAsync(d_nobj, 0, no * sizeof(float2), s));
+    chk(hipMemsetAsync(d_wobj, 0, no * sizeof(float), s));
   }
+  if (n_probe) chk(hipMemsetAsync(c->db.nP, 0, K * nn * sizeof(float2), s));
+  if (v_probe) chk(hipMemsetAsync(c->db.V, 0, nn * sizeof(float), s));
+  if (d_psi) chk(launch_exit_waves(c->dp, c->db, c->d_dbg_order, B, d_psi, s));
+  std::string le;
+  if (e == hipSuccess) le = launch_batch(c->tm.mask ? c : nullptr, c->d_case_dbg, single_shape(c, B), 0, c->d_dbg_iter, s);
+  auto copy = [&](float* dst, const void* src, size_t bytes) {
+    if (dst) chk(hipMemcpyAsync(dst, src, bytes, kind_out(mem_kind), s));
+  };
+  if (e == hipSuccess && le.empty()) {
+    copy(psi, d_psi, (size_t)B * K * nn * sizeof(float2));
+    copy(psi_new, d_psin, (size_t)B * K * nn * sizeof(float2));
+    copy(factor, d_fac, (size_t)B * nn * sizeof(float));
+    copy(n_obj, d_nobj, no * sizeof(float2));
+    copy(w_obj, d_wobj, no * sizeof(float));
+    copy(n_probe, c->db.nP, K * nn * sizeof(float2));
+    copy(v_probe, c->db.V, nn * sizeof(float));
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e2;
   if (c->tm.used) harvest_timing(c);
   cleanup();
-  if (st != PTYCHO_OK) return st;
-  if (e != hipSuccess) return fail(c, PTYCHO_E_HIP, std::string("debug copies: ") + hipGetErrorString(e));
+  if (!le.empty()) return fail(c, PTYCHO_E_HIP, le);
+  if (e != hipSuccess) return fail(c, PTYCHO_E_HIP, std::string("debug step: ") + hipGetErrorString(e));
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_autotune(ptycho_ctx* c, int32_t trials, int32_t force, int32_t* chosen) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
+  if (trials < 1) trials = 1;
+  const int n = c->prm.n;
+  const auto key = std::make_tuple(n, c->prm.n_modes, c->prm.batch, (int)c->prm.geometry);
+  if (!force) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && col_variant_valid(n, it->second)) {
+      if (c->col_variant != it->second) drop_graph(c);
+      c->col_variant = it->second;
+      if (chosen) *chosen = c->col_variant;
+      return PTYCHO_OK;
+    }
+  }
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  // back up the state the timing runs modify
+  const size_t no = (size_t)c->prm.obj_h * c->prm.obj_w, npr = (size_t)c->prm.n_modes * n * n;
+  float2 *bo = nullptr, *bp = nullptr;
+  if (hipMalloc((void**)&bo, no * sizeof(float2)) != hipSuccess) return fail(c, PTYCHO_E_OOM, "autotune backup");
+  if (hipMalloc((void**)&bp, npr * sizeof(float2)) != hipSuccess) {
+    (void)hipFree(bo);
+    return fail(c, PTYCHO_E_OOM, "autotune backup");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  std::string err;
+  int best = c->col_variant;
+  float best_ms = 1e30f;
+  hipError_t he = hipMemcpyAsync(bo, c->db.obj, no * sizeof(float2), hipMemcpyDeviceToDevice, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(bp, c->db.probe, npr * sizeof(float2), hipMemcpyDeviceToDevice, s);
+  const int saved_variant = c->col_variant;
+  ptycho_status st = (he == hipSuccess) ? stage_call(c, 1, nullptr) : PTYCHO_E_HIP;
+  if (st == PTYCHO_OK) {
+    c->call.h_flags[0] = FLAG_PROBE | FLAG_CC;
+    for (int v = 0; v < kColVariants && err.empty(); ++v) {
+      if (!col_variant_valid(n, v)) continue;
+      c->col_variant = v;
+      fill_case(c, *c->h_case, c->call.d_order, c->call.d_flags, c->call.d_err);
+      he = hipMemcpyAsync(c->call.d_order, c->call.h_order, c->prm.n_pos * sizeof(int), hipMemcpyHostToDevice, s);
+      if (he == hipSuccess) he = hipMemcpyAsync(c->call.d_flags, c->call.h_flags, sizeof(int), hipMemcpyHostToDevice, s);
+      if (he == hipSuccess) he = hipMemcpyAsync(c->d_case, c->h_case, sizeof(CaseDesc), hipMemcpyHostToDevice, s);
+      if (he == hipSuccess) he = launch_iter_set(c->d_iter, 0, s);
+      if (he != hipSuccess) {
+        err = hipGetErrorString(he);
+        break;
+      }
+      const TableShape sh = single_shape(c, c->prm.batch);
+      err = launch_batch(nullptr, c->d_case, sh, 0, c->d_iter, s);  // warm-up
+      if (!err.empty()) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < trials && err.empty(); ++r) err = launch_batch(nullptr, c->d_case, sh, 0, c->d_iter, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipStreamSynchronize(s);
+      float ms = 0.f;
+      if (err.empty() && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+  }
+  // restore the state
+  (void)hipMemcpyAsync(c->db.obj, bo, no * sizeof(float2), hipMemcpyDeviceToDevice, s);
+  (void)hipMemcpyAsync(c->db.probe, bp, npr * sizeof(float2), hipMemcpyDeviceToDevice, s);
+  (void)launch_pw(c->dp, c->db, s);
+  hipError_t fin = hipStreamSynchronize(s);
+  (void)hipFree(bo);
+  (void)hipFree(bp);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != PTYCHO_OK) {
+    c->col_variant = saved_variant;
+    return st;
+  }
+  if (!err.empty() || fin != hipSuccess) {
+    c->col_variant = saved_variant;
+    return fail(c, PTYCHO_E_HIP, "autotune: " + (err.empty() ? std::string(hipGetErrorString(fin)) : err));
+  }
+  if (best != saved_variant) drop_graph(c);
+  c->col_variant = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store_locked(key, best);
+  }
+  if (chosen) *chosen = best;
   return PTYCHO_OK;
 }
 
@@ -704,13 +1013,162 @@ int32_t ptycho_kernel_class_count(void) { return KC_COUNT; }
 
 void ptycho_destroy(ptycho_ctx* c) {
   if (!c) return;
-  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+  drop_graph(c);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
   for (void* p : c->allocs) (void)hipFree(p);
-  if (c->h_order) (void)hipHostFree(c->h_order);
+  free_call(c->call);
+  if (c->h_case) (void)hipHostFree(c->h_case);
   delete c;
 }
 
 const char* ptycho_last_error(const ptycho_ctx* c) { return c ? c->err.c_str() : g_thread_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Groups of independent reconstructions
+// ---------------------------------------------------------------------------
+
+ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_group** out) {
+  if (out) *out = nullptr;
+  if (!out || !ctxs || n < 1) return gfail(nullptr, PTYCHO_E_INVALID, "need out and n >= 1 contexts");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return gfail(nullptr, PTYCHO_E_INVALID, "NULL context in group");
+    if (ctxs[i]->failed) return gfail(nullptr, PTYCHO_E_STATE, "a context in the group has failed");
+    if (ctxs[i]->device != ctxs[0]->device || ctxs[i]->stream != ctxs[0]->stream)
+      return gfail(nullptr, PTYCHO_E_INVALID, "group contexts must share one device and stream");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return gfail(nullptr, PTYCHO_E_INVALID, "a context appears twice in the group");
+  }
+  ptycho_group* g = new ptycho_group();
+  g->ctx.assign(ctxs, ctxs + n);
+  g->stream = ctxs[0]->stream;
+  // one table per (frame size, geometry)
+  std::map<std::pair<int, int>, int> idx;
+  for (int i = 0; i < n; ++i) {
+    const ptycho_ctx* c = ctxs[i];
+    const auto key = std::make_pair(c->prm.n, (int)c->prm.geometry);
+    if (!idx.count(key)) {
+      idx[key] = (int)g->tables.size();
+      g->tables.emplace_back();
+      TableShape& sh = g->tables.back().shape;
+      sh.n = c->prm.n;
+      sh.near_field = c->prm.geometry == PTYCHO_NEAR_FIELD;
+      sh.col_variant = c->col_variant;
+    }
+    ptycho_group::Table& tb = g->tables[idx[key]];
+    tb.members.push_back(i);
+    TableShape& sh = tb.shape;
+    sh.n_cases = (int)tb.members.size();
+    sh.max_batch = std::max(sh.max_batch, c->prm.batch);
+    sh.max_tiles = std::max(sh.max_tiles, n_obj_tiles(c->dp));
+    sh.max_k = std::max(sh.max_k, c->prm.n_modes);
+    sh.max_side_jobs = std::max(sh.max_side_jobs, n_obj_tiles(c->dp) + n_probe_blocks(c->prm.n));
+  }
+  for (auto& tb : g->tables) {
+    void* p = nullptr;
+    if (hipMalloc(&p, tb.members.size() * sizeof(CaseDesc)) != hipSuccess) {
+      ptycho_group_destroy(g);
+      return gfail(nullptr, PTYCHO_E_OOM, "group table allocation failed");
+    }
+    g->allocs.push_back(p);
+    tb.d_cases = (CaseDesc*)p;
+    if (hipHostMalloc((void**)&tb.h_cases, tb.members.size() * sizeof(CaseDesc), hipHostMallocDefault) != hipSuccess) {
+      tb.h_cases = nullptr;
+      ptycho_group_destroy(g);
+      return gfail(nullptr, PTYCHO_E_OOM, "pinned host allocation failed");
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(int)) != hipSuccess) {
+    ptycho_group_destroy(g);
+    return gfail(nullptr, PTYCHO_E_OOM, "group counter allocation failed");
+  }
+  g->allocs.push_back(p);
+  g->d_iter = (int*)p;
+  *out = g;
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_out) {
+  if (!g) return gfail(nullptr, PTYCHO_E_INVALID, "group is NULL");
+  if (n_iter < 0) return gfail(g, PTYCHO_E_INVALID, "n_iter must be >= 0");
+  if (n_iter == 0) return PTYCHO_OK;
+  const int nc = (int)g->ctx.size();
+  for (ptycho_ctx* c : g->ctx)
+    if (c->failed) return gfail(g, PTYCHO_E_STATE, "a context in the group has failed: " + c->err);
+  hipStream_t s = g->stream;
+  HIP_GTRY(g, hipStreamSynchronize(s));
+  // schedules of every case, concatenated
+  std::vector<size_t> off(nc + 1, 0);
+  for (int i = 0; i < nc; ++i) off[i + 1] = off[i] + (size_t)n_iter * g->ctx[i]->prm.n_pos;
+  if (!grow_call(g, g->allocs, g->call, off[nc], (size_t)n_iter * nc))
+    return gfail(g, PTYCHO_E_OOM, "schedule buffer allocation failed");
+  int max_nb = 0;
+  for (int i = 0; i < nc; ++i) {
+    ptycho_ctx* c = g->ctx[i];
+    const int np = c->prm.n_pos;
+    for (int it = 0; it < n_iter; ++it) {
+      splitmix_perm(c->prm.seed, c->t + 1 + it, np, g->call.h_order + off[i] + (size_t)it * np);
+      g->call.h_flags[(size_t)i * n_iter + it] = case_flags(c->prm, c->t + 1 + it);
+    }
+    max_nb = std::max(max_nb, n_batches_of(c->prm));
+  }
+  for (auto& tb : g->tables)
+    for (size_t m = 0; m < tb.members.size(); ++m) {
+      const int i = tb.members[m];
+      fill_case(g->ctx[i], tb.h_cases[m], g->call.d_order + off[i], g->call.d_flags + (size_t)i * n_iter,
+                g->call.d_err + (size_t)i * n_iter);
+      tb.h_cases[m].n_err_part = g->ctx[i]->prm.n_pos * n_err_slots(tb.shape.n, tb.shape.col_variant);
+    }
+  HIP_GTRY(g, hipMemcpyAsync(g->call.d_order, g->call.h_order, off[nc] * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_GTRY(g, hipMemcpyAsync(g->call.d_flags, g->call.h_flags, (size_t)n_iter * nc * sizeof(int),
+                             hipMemcpyHostToDevice, s));
+  for (auto& tb : g->tables)
+    HIP_GTRY(g, hipMemcpyAsync(tb.d_cases, tb.h_cases, tb.members.size() * sizeof(CaseDesc), hipMemcpyHostToDevice, s));
+  HIP_GTRY(g, launch_iter_set(g->d_iter, 0, s));
+  for (int it = 0; it < n_iter; ++it) {
+    for (int beta = 0; beta < max_nb; ++beta)
+      for (auto& tb : g->tables) {
+        std::string e = launch_batch(nullptr, tb.d_cases, tb.shape, beta, g->d_iter, s);
+        if (!e.empty()) return gfail(g, PTYCHO_E_HIP, e);
+      }
+    for (auto& tb : g->tables) {
+      std::string e = launch_end(nullptr, tb.d_cases, tb.shape, g->d_iter, s);
+      if (!e.empty()) return gfail(g, PTYCHO_E_HIP, e);
+    }
+    HIP_GTRY(g, launch_iter_advance(g->d_iter, s));
+  }
+  HIP_GTRY(g, hipMemcpyAsync(g->call.h_err, g->call.d_err, (size_t)n_iter * nc * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_GTRY(g, hipStreamSynchronize(s));
+  ptycho_status st = PTYCHO_OK;
+  for (int i = 0; i < nc; ++i) {
+    ptycho_ctx* c = g->ctx[i];
+    c->t += n_iter;
+    for (int it = 0; it < n_iter; ++it)
+      if (!std::isfinite(g->call.h_err[(size_t)i * n_iter + it]) && !c->failed) {
+        c->failed = true;
+        c->err = "non-finite data error at iteration " + std::to_string(c->t - n_iter + 1 + it);
+        st = gfail(g, PTYCHO_E_NUMERIC, "case " + std::to_string(i) + ": " + c->err);
+      }
+  }
+  if (err_out) std::memcpy(err_out, g->call.h_err, (size_t)n_iter * nc * sizeof(float));
+  return st;
+}
+
+void ptycho_group_destroy(ptycho_group* g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  for (auto& tb : g->tables)
+    if (tb.h_cases) (void)hipHostFree(tb.h_cases);
+  for (void* p : g->allocs) (void)hipFree(p);
+  free_call(g->call);
+  delete g;
+}
+
+const char* ptycho_group_last_error(const ptycho_group* g) { return g ? g->err.c_str() : g_thread_error.c_str(); }
 
 }  // extern "C"

@@ -25,7 +25,8 @@ __all__ = [
     "ptycho_init", "ptycho_iterate", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
     "ptycho_permutation", "ptycho_set_timing", "ptycho_kernel_time", "kernel_names",
-    "Reconstruction",
+    "ptycho_set_graph", "ptycho_autotune", "ptycho_group_create", "ptycho_group_iterate",
+    "ptycho_group_destroy", "ptycho_group_last_error", "Reconstruction", "Group",
 ]
 
 PTYCHO_OK, PTYCHO_E_INVALID, PTYCHO_E_SHAPE, PTYCHO_E_OOM = 0, -1, -2, -3
@@ -95,6 +96,12 @@ def load_library():
         "ptycho_destroy": (None, [vp]),
         "ptycho_last_error": (ctypes.c_char_p, [vp]),
         "ptycho_permutation": (i32, [u64, i32, i32, fp]),
+        "ptycho_set_graph": (i32, [vp, i32]),
+        "ptycho_autotune": (i32, [vp, i32, i32, P(i32)]),
+        "ptycho_group_create": (i32, [P(vp), i32, P(vp)]),
+        "ptycho_group_iterate": (i32, [vp, i32, fp]),
+        "ptycho_group_destroy": (None, [vp]),
+        "ptycho_group_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -270,6 +277,73 @@ def kernel_names():
     return [L.ptycho_kernel_name(i).decode() for i in range(L.ptycho_kernel_class_count())]
 
 
+def ptycho_set_graph(ctx, enable):
+    _check(load_library().ptycho_set_graph(ctx, 1 if enable else 0), ctx)
+
+
+def ptycho_autotune(ctx, trials=3, force=False):
+    """Time the column-tile variants on the context's first batch; returns the chosen index."""
+    chosen = ctypes.c_int32(-1)
+    _check(load_library().ptycho_autotune(ctx, int(trials), 1 if force else 0, ctypes.byref(chosen)), ctx)
+    return chosen.value
+
+
+def ptycho_group_last_error(group=None):
+    m = load_library().ptycho_group_last_error(group)
+    return m.decode() if m else ""
+
+
+def _gcheck(status, group):
+    if status != PTYCHO_OK:
+        raise PtychoError(status, ptycho_group_last_error(group))
+
+
+def ptycho_group_create(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    out = ctypes.c_void_p()
+    _gcheck(load_library().ptycho_group_create(arr, len(ctxs), ctypes.byref(out)), None)
+    return out
+
+
+def ptycho_group_iterate(group, n_iter, n_cases):
+    err = np.zeros((n_cases, max(int(n_iter), 1)), dtype=np.float32)
+    _gcheck(load_library().ptycho_group_iterate(group, int(n_iter), ctypes.c_void_p(err.ctypes.data)), group)
+    return err[:, :n_iter] if n_iter else err[:, :0]
+
+
+def ptycho_group_destroy(group):
+    if group:
+        load_library().ptycho_group_destroy(group)
+
+
+class Group:
+    """A group of Reconstruction objects iterated together (they must outlive it)."""
+
+    def __init__(self, recs):
+        self.recs = list(recs)
+        self.g = ptycho_group_create([r.ctx for r in self.recs])
+
+    def iterate(self, n_iter):
+        return ptycho_group_iterate(self.g, n_iter, len(self.recs))
+
+    def close(self):
+        if self.g:
+            ptycho_group_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 class Reconstruction:
     """Owning wrapper of one context (host numpy inputs)."""
 
@@ -292,6 +366,12 @@ class Reconstruction:
 
     def set_state(self, obj=None, probe=None, iteration=0):
         ptycho_set_state(self.ctx, obj, probe, iteration)
+
+    def set_graph(self, enable=True):
+        ptycho_set_graph(self.ctx, enable)
+
+    def autotune(self, trials=3, force=False):
+        return ptycho_autotune(self.ctx, trials, force)
 
     @property
     def iteration(self):
