@@ -77,6 +77,13 @@ typedef struct ptycho_params {
   int32_t batch;                 /* positions per update, [1, 256]; 1 = sequential ePIE */
   int32_t orthogonalize;         /* 1: orthogonalise the K > 1 modes after each iteration */
   uint64_t seed;                 /* random sequence S_n when no explicit order is given */
+  /* 1: propagate by the unitary DFT as dense complex GEMMs on BF16 matrix cores
+   * with a two-term split of both operands (x = x_hi + x_lo) and FP32
+   * accumulation, instead of the FP32 FFT passes.  Far field, n in {64, 128, 256}.
+   * The modulus constraint, the step normalisation and the mode
+   * orthogonalisation stay in FP32.  Results differ from the FP32 path by the
+   * split's rounding (about 1e-5 relative per transform). */
+  int32_t dft_bf16;
 } ptycho_params;
 
 /* Fill *p with defaults: n = 64, K = 1, far field, sigma 1, kernel 11, amplitude
@@ -186,6 +193,12 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
 ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_out);
 void ptycho_group_destroy(ptycho_group* g);
 const char* ptycho_group_last_error(const ptycho_group* g);
+
+/* The unitary 2D DFT (inverse != 0: its inverse) of `frames` device frames
+ * [frames][n][n][2] in place, by the BF16-split matrix-core GEMMs of the
+ * dft_bf16 path (n in {64, 128, 256}), ordered on hip_stream (NULL = null stream);
+ * synchronises it.  For measuring that path's error and speed on its own. */
+ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, int32_t inverse, void* hip_stream);
 
 /* Host-only: the order used for iteration t when none is given -- Fisher-Yates
  * over 0..n_pos-1 (for i = n_pos-1 .. 1: j = next % (i + 1), swap) with `next`

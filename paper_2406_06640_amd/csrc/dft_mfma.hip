@@ -1,0 +1,368 @@
+// Far-field propagation as dense complex GEMMs on BF16 matrix cores (gfx950).
+//
+// The unitary 2D DFT of a frame X is F X F with F[u][x] = exp(-2 pi i u x / N) / sqrt(N)
+// (F is symmetric); the inverse uses conj(F).  Each frame is transformed by a
+// "right" GEMM (every row times F) and a "left" GEMM (F times every column).
+// Operands are split into two BF16 parts, x = x_hi + x_lo, f = f_hi + f_lo,
+// and each real product is x_hi f_hi + x_hi f_lo + x_lo f_hi (the x_lo f_lo
+// term, ~2^-18 relative, is dropped), accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16.  A complex product is four real products.
+// The modulus constraint, the step normalisation and the probe update stay
+// in FP32 (the same kernels as the FFT path).
+//
+// MFMA 16x16x32 operand layout (lane l of a wave64): A[row = l % 16][k = 8 (l / 16) + i],
+// B[k = 8 (l / 16) + i][col = l % 16], i = 0..7; result C[row = 4 (l / 16) + i][col = l % 16], i = 0..3.
+//
+// This file is included by kernels.hip (it shares its device helpers).
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace pty {
+
+__device__ __forceinline__ floatx4 mma(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const __bf16 h = (__bf16)v[i];
+    hi[i] = h;
+    lo[i] = (__bf16)(v[i] - (float)h);
+  }
+}
+
+__device__ __forceinline__ bf16x8 neg8(bf16x8 a) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = -a[i];
+  return a;
+}
+
+// acc += (a_hi + a_lo)(b_hi + b_lo) without the lo*lo term
+__device__ __forceinline__ floatx4 mma3(bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 bl, floatx4 c) {
+  c = mma(ah, bh, c);
+  c = mma(ah, bl, c);
+  c = mma(al, bh, c);
+  return c;
+}
+
+// DFT table planes [4][N][N] (re_hi, re_lo, im_hi, im_lo) of F, row-major [u][x].
+struct DftPlanes {
+  const __bf16* p;
+  __device__ __forceinline__ bf16x8 load(int plane, int n, int row, int k) const {
+    return *reinterpret_cast<const bf16x8*>(p + ((size_t)plane * n + row) * n + k);
+  }
+};
+
+// Complex product of one 16 x 32 A fragment (split re/im) with one 32 x 16 B fragment.
+// conj_b: use conj(B).
+struct CFrag {
+  bf16x8 rh, rl, ih, il;
+};
+__device__ __forceinline__ void cmma(const CFrag& a, const CFrag& b, bool conj_b, floatx4& cr, floatx4& ci) {
+  // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br);  conj(b): bi -> -bi
+  cr = mma3(a.rh, a.rl, b.rh, b.rl, cr);
+  if (!conj_b) {
+    cr = mma3(neg8(a.ih), neg8(a.il), b.ih, b.il, cr);
+    ci = mma3(a.rh, a.rl, b.ih, b.il, ci);
+  } else {
+    cr = mma3(a.ih, a.il, b.ih, b.il, cr);
+    ci = mma3(neg8(a.rh), neg8(a.rl), b.ih, b.il, ci);
+  }
+  ci = mma3(a.ih, a.il, b.rh, b.rl, ci);
+}
+
+// Rows of every frame times F (or conj F): X[r][:] <- X[r][:] F, in place.
+// Block = 16 rows; wave w produces output columns [w N/4, (w+1) N/4).
+template <int N, bool INV>
+__global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows) {
+  constexpr int TPW = N / 64;  // 16-column tiles per wave
+  const int r0 = blockIdx.x * 16;
+  if (r0 >= rows) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, kq = lane >> 4;
+  floatx4 cr[TPW], ci[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    cr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  const float2* xrow = X + (size_t)(r0 + lr) * N;
+  for (int kc = 0; kc < N; kc += 32) {
+    const int k0 = kc + kq * 8;
+    float re[8], im[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float2 v = xrow[k0 + i];
+      re[i] = v.x;
+      im[i] = v.y;
+    }
+    CFrag a;
+    split8(re, a.rh, a.rl);
+    split8(im, a.ih, a.il);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int col = w * (N / 4) + t * 16 + lr;  // B[k][col] = F[col][k]
+      CFrag b{F.load(0, N, col, k0), F.load(1, N, col, k0), F.load(2, N, col, k0), F.load(3, N, col, k0)};
+      cmma(a, b, INV, cr[t], ci[t]);
+    }
+  }
+  __syncthreads();  // every wave has read the block's rows before any is overwritten
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int col = w * (N / 4) + t * 16 + lr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[(size_t)(r0 + kq * 4 + i) * N + col] = make_float2(cr[t][i], ci[t][i]);
+  }
+}
+
+// F (or conj F) times every column of each frame: X_f <- F X_f, in place.
+// Block = 16 columns of one frame (blockIdx.y); wave w produces rows [w N/4, (w+1) N/4).
+template <int N, bool INV>
+__global__ __launch_bounds__(256) void k_dft_left(float2* __restrict__ X, DftPlanes F, int frames) {
+  constexpr int TPW = N / 64;
+  const int f = blockIdx.y;
+  if (f >= frames) return;
+  const int c0 = blockIdx.x * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lc = lane & 15, kq = lane >> 4;
+  float2* fr = X + (size_t)f * N * N;
+  floatx4 cr[TPW], ci[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    cr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int kc = 0; kc < N; kc += 32) {
+    const int k0 = kc + kq * 8;
+    float re[8], im[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {  // B[k][col] = X[k][c0 + col]
+      const float2 v = fr[(size_t)(k0 + i) * N + c0 + lc];
+      re[i] = v.x;
+      im[i] = v.y;
+    }
+    CFrag b;
+    split8(re, b.rh, b.rl);
+    split8(im, b.ih, b.il);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int row = w * (N / 4) + t * 16 + lc;  // A[row][k] = F[row][k]
+      CFrag a{F.load(0, N, row, k0), F.load(1, N, row, k0), F.load(2, N, row, k0), F.load(3, N, row, k0)};
+      if (INV) {  // conj(F) X: negate the imaginary part of the table operand
+        a.ih = neg8(a.ih);
+        a.il = neg8(a.il);
+      }
+      cmma(a, b, false, cr[t], ci[t]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int row0 = w * (N / 4) + t * 16 + kq * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fr[(size_t)(row0 + i) * N + c0 + lc] = make_float2(cr[t][i], ci[t][i]);
+  }
+}
+
+// Exit waves of the batch into the work frames: X[b][k] = o_b P_k.
+__global__ __launch_bounds__(kThreads) void k_dft_exit(const CaseDesc* __restrict__ cases, int beta,
+                                                       const int* __restrict__ it) {
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const int n = p.n, K = p.k;
+  const size_t nn = (size_t)n * n;
+  const int per = (n * n + kThreads - 1) / kThreads;
+  const int b = blockIdx.x / per, pix = (blockIdx.x % per) * kThreads + threadIdx.x;
+  if (b >= bt.ns || pix >= n * n) return;
+  const int2 rc = d.pos[bt.slots[b]];
+  const int y = pix / n, x = pix - y * n;
+  const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
+  for (int k = 0; k < K; ++k) d.X[((size_t)b * K + k) * nn + pix] = cmul(o, d.probe[(size_t)k * nn + pix]);
+}
+
+// Side work of the batch (see side_job) as its own launch.
+__global__ __launch_bounds__(kThreads) void k_dft_side(const CaseDesc* __restrict__ cases, int beta,
+                                                       const int* __restrict__ it) {
+  __shared__ SideScratch sc;
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  side_job(bt.cs->p, bt.cs->d, bt.slots, bt.ns, blockIdx.x, (bt.flags & FLAG_PROBE) != 0, sc);
+}
+
+// q[b] = sum_k |Psi_k|^2 (intensity blur) or its square root (amplitude blur).
+__global__ __launch_bounds__(kThreads) void k_dft_modsum(const CaseDesc* __restrict__ cases, int beta,
+                                                         const int* __restrict__ it) {
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const int n = p.n, K = p.k;
+  const size_t nn = (size_t)n * n;
+  const int per = (n * n + kThreads - 1) / kThreads;
+  const int b = blockIdx.x / per, pix = (blockIdx.x % per) * kThreads + threadIdx.x;
+  if (b >= bt.ns || pix >= n * n) return;
+  float s = 0.f;
+  for (int k = 0; k < K; ++k) {
+    const float2 v = d.X[((size_t)b * K + k) * nn + pix];
+    s += v.x * v.x + v.y * v.y;
+  }
+  d.q[(size_t)b * nn + pix] = p.blur_intensity ? s : sqrtf(s);
+}
+
+// Separable periodic blur of q over a 32 x 32 tile (halo in LDS), the modulus
+// factor of box 1, the data error, and Psi_k *= factor for every mode.
+constexpr int kDftTile = 32;
+__global__ __launch_bounds__(kThreads) void k_dft_blur_apply(const CaseDesc* __restrict__ cases, int beta,
+                                                             const int* __restrict__ it) {
+  constexpr int S = kDftTile + 2 * kMaxHalf;
+  __shared__ float qs[S][S + 1];
+  __shared__ float hs[S][kDftTile + 1];
+  __shared__ double red[kThreads / 64];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const int n = p.n, K = p.k;
+  const int tpr = n / kDftTile, tiles = tpr * tpr;
+  const int b = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  if (b >= bt.ns) return;
+  const int ty0 = (tile / tpr) * kDftTile, tx0 = (tile % tpr) * kDftTile;
+  const int h = p.ks_half, s = kDftTile + 2 * h;
+  const size_t nn = (size_t)n * n;
+  const float* q = d.q + (size_t)b * nn;
+  for (int e = threadIdx.x; e < s * s; e += kThreads) {
+    const int yy = e / s, xx = e - yy * s;
+    qs[yy][xx] = q[(size_t)wrap(ty0 - h + yy, n) * n + wrap(tx0 - h + xx, n)];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < s * kDftTile; e += kThreads) {
+    const int yy = e / kDftTile, x = e - yy * kDftTile;
+    float acc = p.gx[0] * qs[yy][x + h];
+    for (int dx = 1; dx <= h; ++dx) acc += p.gx[dx] * (qs[yy][x + h - dx] + qs[yy][x + h + dx]);
+    hs[yy][x] = acc;
+  }
+  __syncthreads();
+  const int pat = bt.slots[b];
+  const float* amp = d.amp + (size_t)pat * nn;
+  float* dbgf = bt.cs->dbg.factor ? bt.cs->dbg.factor + (size_t)b * nn : nullptr;
+  double err = 0.0;
+  for (int e = threadIdx.x; e < kDftTile * kDftTile; e += kThreads) {
+    const int y = e / kDftTile, x = e - y * kDftTile;
+    float g = p.gy[0] * hs[y + h][x];
+    for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (hs[y + h - dy][x] + hs[y + h + dy][x]);
+    const size_t idx = (size_t)(ty0 + y) * n + tx0 + x;
+    const float a = amp[idx];
+    float ag, f;
+    if (p.blur_intensity) {
+      ag = sqrtf(g);
+      f = a / sqrtf(g + p.eps * p.eps);
+    } else {
+      ag = g;
+      f = a / (g + p.eps);
+    }
+    if (dbgf) dbgf[idx] = f;
+    const double dd = (double)a - (double)ag;
+    err += dd * dd;
+    for (int k = 0; k < K; ++k) {
+      float2* xv = d.X + ((size_t)b * K + k) * nn + idx;
+      *xv = cscale(*xv, f);
+    }
+  }
+  const double tot = block_sum_d(err, red);
+  if (threadIdx.x == 0) d.err_part[(size_t)pat * tiles + tile] = tot;
+}
+
+// psi' is in X: dpsi = psi' - o_b P_k; per-slot object numerator sum_k conj(P_k) dpsi_k;
+// X <- conj(o_b) dpsi_k (the probe contributions).
+__global__ __launch_bounds__(kThreads) void k_dft_delta(const CaseDesc* __restrict__ cases, int beta,
+                                                        const int* __restrict__ it) {
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufs d = bt.cs->d;
+  const int n = p.n, K = p.k;
+  const size_t nn = (size_t)n * n;
+  const int per = (n * n + kThreads - 1) / kThreads;
+  const int b = blockIdx.x / per, pix = (blockIdx.x % per) * kThreads + threadIdx.x;
+  if (b >= bt.ns || pix >= n * n) return;
+  const int2 rc = d.pos[bt.slots[b]];
+  const int y = pix / n, x = pix - y * n;
+  const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
+  float2* dbgp = bt.cs->dbg.psi_new;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int k = 0; k < K; ++k) {
+    float2* xv = d.X + ((size_t)b * K + k) * nn + pix;
+    const float2 psi_new = *xv;
+    if (dbgp) dbgp[((size_t)b * K + k) * nn + pix] = psi_new;
+    const float2 pv = d.probe[(size_t)k * nn + pix];
+    const float2 dpsi = csub(psi_new, cmul(o, pv));
+    acc = cadd(acc, cmulc(dpsi, pv));
+    *xv = cmulc(dpsi, o);
+  }
+  d.dO[(size_t)b * nn + pix] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+bool dft_supported(int n) { return n == 64 || n == 128 || n == 256; }
+int dft_err_slots(int n) { return (n / kDftTile) * (n / kDftTile); }
+
+template <int N>
+static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inverse, hipStream_t s) {
+  DftPlanes F{planes};
+  const int rows = frames * N;
+  if (!inverse) {
+    hipLaunchKernelGGL((k_dft_right<N, false>), dim3(rows / 16), dim3(256), 0, s, X, F, rows);
+    hipLaunchKernelGGL((k_dft_left<N, false>), dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
+  } else {
+    hipLaunchKernelGGL((k_dft_left<N, true>), dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
+    hipLaunchKernelGGL((k_dft_right<N, true>), dim3(rows / 16), dim3(256), 0, s, X, F, rows);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dft2(float2* X, const void* planes, int n, int frames, bool inverse, hipStream_t s) {
+  const __bf16* pl = static_cast<const __bf16*>(planes);
+  switch (n) {
+    case 64: return dft2_t<64>(X, pl, frames, inverse, s);
+    case 128: return dft2_t<128>(X, pl, frames, inverse, s);
+    case 256: return dft2_t<256>(X, pl, frames, inverse, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static int pix_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
+
+hipError_t launch_dft_side(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dft_side, dim3(t.max_side_jobs, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  return hipGetLastError();
+}
+hipError_t launch_dft_exit(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dft_exit, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
+                     it);
+  return hipGetLastError();
+}
+hipError_t launch_dft_modsum(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dft_modsum, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
+                     it);
+  return hipGetLastError();
+}
+hipError_t launch_dft_blur_apply(const CaseDesc* cases, const TableShape& t, int beta, const int* it,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_dft_blur_apply, dim3(dft_err_slots(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s,
+                     cases, beta, it);
+  return hipGetLastError();
+}
+hipError_t launch_dft_delta(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_dft_delta, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
+                     it);
+  return hipGetLastError();
+}
+
+}  // namespace pty

@@ -28,7 +28,7 @@ namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
     "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_update", "probe_update_constraint",
-    "gram", "eig", "mode_remix", "err_reduce"};
+    "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise"};
 
 constexpr int kThreads = 256;
 
@@ -139,10 +139,6 @@ __device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots,
                          SideScratch& sc);
 
 // Blocks with blockIdx.y >= ns do the batch's side work (see side_job).
-struct SideScratch;
-__device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
-                         SideScratch& sc);
-
 // Row pass 1.  Blocks past the case's slots do the batch's side work (side_job).
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
@@ -1146,3 +1142,5 @@ hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* sl
 }
 
 }  // namespace pty
+
+#include "dft_mfma.hip"

@@ -92,7 +92,7 @@ struct TableShape {
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_POST, KC_GRAM, KC_EIG, KC_REMIX,
-  KC_ERR, KC_COUNT
+  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -119,6 +119,17 @@ hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, 
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s);
 hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* slots, int ns, float2* out,
                              hipStream_t s);
+
+// BF16 matrix-core DFT path (far field, n in {64, 128, 256}); single table only.
+// planes: [4][n][n] bf16 (re_hi, re_lo, im_hi, im_lo) of F[u][x] = exp(-2 pi i u x / n) / sqrt(n).
+bool dft_supported(int n);
+int dft_err_slots(int n);
+hipError_t launch_dft2(float2* X, const void* planes, int n, int frames, bool inverse, hipStream_t s);
+hipError_t launch_dft_side(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_dft_exit(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_dft_modsum(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_dft_blur_apply(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_dft_delta(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 
 int n_obj_tiles(const DevParams& p);
 int n_err_slots(int n, int col_variant);  // data-error partials per position (one per column block)

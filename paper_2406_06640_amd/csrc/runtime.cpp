@@ -70,6 +70,7 @@ struct ptycho_ctx {
   int* d_dbg_iter = nullptr;
   float* d_dbg_err = nullptr;
   int col_variant = 1;
+  void* d_planes = nullptr;  // bf16 DFT table planes (dft_bf16 path)
   // graph replay of one iteration
   bool use_graph = false;
   hipStream_t gstream = nullptr;
@@ -147,6 +148,9 @@ std::string validate(const ptycho_params* p) {
     return "gamma_obj, gamma_probe must be in (0,1]";
   if (p->batch < 1 || p->batch > kMaxBatch) return "batch must be in [1,256]";
   if (p->orthogonalize != 0 && p->orthogonalize != 1) return "orthogonalize must be 0 or 1";
+  if (p->dft_bf16 != 0 && p->dft_bf16 != 1) return "dft_bf16 must be 0 or 1";
+  if (p->dft_bf16 && (p->geometry != PTYCHO_FAR_FIELD || !dft_supported(p->n)))
+    return "dft_bf16 needs the far field and n in {64, 128, 256}";
   return "";
 }
 
@@ -346,7 +350,7 @@ void fill_case(const ptycho_ctx* c, CaseDesc& cd, const int* order, const int* f
   cd.n_pos = c->prm.n_pos;
   cd.batch = c->prm.batch;
   cd.n_batches = n_batches_of(c->prm);
-  cd.n_err_part = c->prm.n_pos * n_err_slots(c->prm.n, c->col_variant);
+  cd.n_err_part = c->prm.n_pos * (c->prm.dft_bf16 ? dft_err_slots(c->prm.n) : n_err_slots(c->prm.n, c->col_variant));
 }
 
 TableShape single_shape(const ptycho_ctx* c, int max_batch) {
@@ -362,13 +366,72 @@ TableShape single_shape(const ptycho_ctx* c, int max_batch) {
   return sh;
 }
 
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_val(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Host-built split planes [4][n][n] (re_hi, re_lo, im_hi, im_lo) of
+// F[u][x] = exp(-2 pi i u x / n) / sqrt(n), evaluated in double.
+std::vector<uint16_t> dft_planes(int n) {
+  std::vector<uint16_t> pl((size_t)4 * n * n);
+  const double pi = 3.14159265358979323846, sc = 1.0 / std::sqrt((double)n);
+  for (int u = 0; u < n; ++u)
+    for (int x = 0; x < n; ++x) {
+      const double a = -2.0 * pi * (double)(((long long)u * x) % n) / n;
+      const double v[2] = {std::cos(a) * sc, std::sin(a) * sc};
+      for (int c = 0; c < 2; ++c) {
+        const uint16_t hi = bf16_rne((float)v[c]);
+        const uint16_t lo = bf16_rne((float)(v[c] - (double)bf16_val(hi)));
+        pl[((size_t)(2 * c) * n + u) * n + x] = hi;
+        pl[((size_t)(2 * c + 1) * n + u) * n + x] = lo;
+      }
+    }
+  return pl;
+}
+
+// The batch of the dft_bf16 path: the same updates as launch_batch, with the
+// two FFT passes per direction replaced by BF16 matrix-core DFT GEMMs.
+std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, const TableShape& sh,
+                             int beta, int ns, const int* it, hipStream_t s) {
+  const int frames = ns * c->prm.n_modes;
+  float2* X = c->db.X;
+  LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_side(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_exit(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, false, s));
+  LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_modsum(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_blur_apply(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, true, s));
+  LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_delta(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_POST, s, launch_post(cases, sh, beta, it, s));
+  return "";
+}
+
+// One batch of a single context (either propagation path).
+std::string launch_one(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, const TableShape& sh, int beta,
+                       int ns, const int* it, hipStream_t s) {
+  if (c->prm.dft_bf16) return launch_batch_dft(tc, c, cases, sh, beta, ns, it, s);
+  return launch_batch(tc, cases, sh, beta, it, s);
+}
+
 // One iteration of a single context on stream s (eager or under capture).
 std::string enqueue_iteration(ptycho_ctx* c, hipStream_t s, bool timed) {
   const TableShape sh = single_shape(c, c->prm.batch);
   ptycho_ctx* tc = timed ? c : nullptr;
   const int nb = n_batches_of(c->prm);
   for (int beta = 0; beta < nb; ++beta) {
-    std::string e = launch_batch(tc, c->d_case, sh, beta, c->d_iter, s);
+    const int ns = std::min(c->prm.batch, c->prm.n_pos - beta * c->prm.batch);
+    std::string e = launch_one(tc, c, c->d_case, sh, beta, ns, c->d_iter, s);
     if (!e.empty()) return e;
   }
   std::string e = launch_end(tc, c->d_case, sh, c->d_iter, s);
@@ -588,7 +651,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   double *errp, *eig;
   double2 *ccp, *gramp;
   const int nobjt = n_obj_tiles(dp);
-  const int nbt = max_err_slots(n);
+  const int nbt = std::max(max_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
   ptycho_status st = PTYCHO_OK;
   if ((st = dev_alloc(c, &obj, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &probe, K * nn)) ||
       (st = dev_alloc(c, &pw, nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
@@ -654,6 +717,14 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   INIT_TRY(hipMemcpyAsync(tw, htw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s));
   INIT_TRY(hipMemcpyAsync(hn, hh.data(), n * sizeof(float2), hipMemcpyHostToDevice, s));
   INIT_TRY(hipMemcpyAsync(pos, hp2.data(), p.n_pos * sizeof(int2), hipMemcpyHostToDevice, s));
+  std::vector<uint16_t> planes;
+  if (p.dft_bf16) {
+    planes = dft_planes(n);
+    uint16_t* dpl = nullptr;
+    if ((st = dev_alloc(c, &dpl, planes.size())) != PTYCHO_OK) return bail(st);
+    c->d_planes = dpl;
+    INIT_TRY(hipMemcpyAsync(dpl, planes.data(), planes.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+  }
   INIT_TRY(hipMemcpyAsync(obj, object0, (size_t)p.obj_h * p.obj_w * sizeof(float2), kind_in(mem_kind), s));
   INIT_TRY(hipMemcpyAsync(probe, probe0, K * nn * sizeof(float2), kind_in(mem_kind), s));
   INIT_TRY(hipMemsetAsync(errp, 0, (size_t)p.n_pos * nbt * sizeof(double), s));
@@ -876,7 +947,8 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   if (v_probe) chk(hipMemsetAsync(c->db.V, 0, nn * sizeof(float), s));
   if (d_psi) chk(launch_exit_waves(c->dp, c->db, c->d_dbg_order, B, d_psi, s));
   std::string le;
-  if (e == hipSuccess) le = launch_batch(c->tm.mask ? c : nullptr, c->d_case_dbg, single_shape(c, B), 0, c->d_dbg_iter, s);
+  if (e == hipSuccess)
+    le = launch_one(c->tm.mask ? c : nullptr, c, c->d_case_dbg, single_shape(c, B), 0, B, c->d_dbg_iter, s);
   auto copy = [&](float* dst, const void* src, size_t bytes) {
     if (dst) chk(hipMemcpyAsync(dst, src, bytes, kind_out(mem_kind), s));
   };
@@ -903,6 +975,10 @@ ptycho_status ptycho_autotune(ptycho_ctx* c, int32_t trials, int32_t force, int3
   if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
   if (trials < 1) trials = 1;
   const int n = c->prm.n;
+  if (c->prm.dft_bf16) {  // the column passes are not used by this path
+    if (chosen) *chosen = c->col_variant;
+    return PTYCHO_OK;
+  }
   const auto key = std::make_tuple(n, c->prm.n_modes, c->prm.batch, (int)c->prm.geometry);
   if (!force) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1038,6 +1114,7 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return gfail(nullptr, PTYCHO_E_INVALID, "NULL context in group");
     if (ctxs[i]->failed) return gfail(nullptr, PTYCHO_E_STATE, "a context in the group has failed");
+    if (ctxs[i]->prm.dft_bf16) return gfail(nullptr, PTYCHO_E_INVALID, "groups run the FFT path only (dft_bf16 = 0)");
     if (ctxs[i]->device != ctxs[0]->device || ctxs[i]->stream != ctxs[0]->stream)
       return gfail(nullptr, PTYCHO_E_INVALID, "group contexts must share one device and stream");
     for (int j = 0; j < i; ++j)
@@ -1167,6 +1244,38 @@ void ptycho_group_destroy(ptycho_group* g) {
   for (void* p : g->allocs) (void)hipFree(p);
   free_call(g->call);
   delete g;
+}
+
+ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, int32_t inverse, void* hip_stream) {
+  if (!frames_inout || frames < 0 || !dft_supported(n))
+    return fail(nullptr, PTYCHO_E_INVALID, "need device frames and n in {64, 128, 256}");
+  if (frames == 0) return PTYCHO_OK;
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, void*> cache;  // (device, n) -> planes; kept for the process
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, PTYCHO_E_HIP, "no HIP device");
+  void* planes = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({dev, n});
+    if (it == cache.end()) {
+      std::vector<uint16_t> pl = dft_planes(n);
+      if (hipMalloc(&planes, pl.size() * sizeof(uint16_t)) != hipSuccess)
+        return fail(nullptr, PTYCHO_E_OOM, "DFT table allocation failed");
+      if (hipMemcpy(planes, pl.data(), pl.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(planes);
+        return fail(nullptr, PTYCHO_E_HIP, "DFT table upload failed");
+      }
+      cache[{dev, n}] = planes;
+    } else {
+      planes = it->second;
+    }
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = launch_dft2(reinterpret_cast<float2*>(frames_inout), planes, n, frames, inverse != 0, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(nullptr, PTYCHO_E_HIP, std::string("dft2_bf16: ") + hipGetErrorString(e));
+  return PTYCHO_OK;
 }
 
 const char* ptycho_group_last_error(const ptycho_group* g) { return g ? g->err.c_str() : g_thread_error.c_str(); }

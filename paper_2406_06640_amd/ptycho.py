@@ -25,7 +25,7 @@ __all__ = [
     "ptycho_init", "ptycho_iterate", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
     "ptycho_permutation", "ptycho_set_timing", "ptycho_kernel_time", "kernel_names",
-    "ptycho_set_graph", "ptycho_autotune", "ptycho_group_create", "ptycho_group_iterate",
+    "ptycho_set_graph", "ptycho_autotune", "ptycho_dft2_bf16", "ptycho_group_create", "ptycho_group_iterate",
     "ptycho_group_destroy", "ptycho_group_last_error", "Reconstruction", "Group",
 ]
 
@@ -56,6 +56,7 @@ class PtychoParams(ctypes.Structure):
         ("gamma_obj", ctypes.c_float), ("gamma_probe", ctypes.c_float),
         ("probe_update_start", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("orthogonalize", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("dft_bf16", ctypes.c_int32),
     ]
 
 
@@ -97,6 +98,7 @@ def load_library():
         "ptycho_last_error": (ctypes.c_char_p, [vp]),
         "ptycho_permutation": (i32, [u64, i32, i32, fp]),
         "ptycho_set_graph": (i32, [vp, i32]),
+        "ptycho_dft2_bf16": (i32, [fp, i32, i32, i32, vp]),
         "ptycho_autotune": (i32, [vp, i32, i32, P(i32)]),
         "ptycho_group_create": (i32, [P(vp), i32, P(vp)]),
         "ptycho_group_iterate": (i32, [vp, i32, fp]),
@@ -275,6 +277,18 @@ def ptycho_kernel_time(ctx, cls, reset=False):
 def kernel_names():
     L = load_library()
     return [L.ptycho_kernel_name(i).decode() for i in range(L.ptycho_kernel_class_count())]
+
+
+def ptycho_dft2_bf16(frames, inverse=False, stream=None):
+    """In-place unitary 2D DFT of a contiguous complex64 CUDA tensor [F][n][n] on the BF16 matrix-core path."""
+    if not _is_torch(frames) or not frames.is_cuda or not frames.is_contiguous():
+        raise ValueError("frames must be a contiguous complex64 CUDA tensor")
+    f, n, n2 = frames.shape
+    if n != n2:
+        raise ValueError("frames must be square")
+    _check(load_library().ptycho_dft2_bf16(ctypes.c_void_p(frames.data_ptr()), n, f, 1 if inverse else 0,
+                                           _stream_handle(stream)), None)
+    return frames
 
 
 def ptycho_set_graph(ctx, enable):
