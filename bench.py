@@ -83,6 +83,39 @@ def cpu_baseline(s, spec, batch, n_batches):
             f"({n_batches * batch} of {len(s['positions'])} positions) of iteration 1, {wall:.1f} s wall"}
 
 
+def warm_start_leg(n_iter):
+    """Second metric: wall seconds to an object-error (NMSE) threshold on scans of the 64 x 64,
+    100-position recipe with coherence blur sigma in {0.5, 1, 2, 3} px, 1e5 counts.  The plain
+    start (sigma 1, flat-phase aperture, one mode) runs each case alone; the learned start
+    (network-predicted settings) runs all cases as one group with graph replay.  NMSE 1e-3 lies
+    below these scans' noise floor, so the threshold of each case is the smallest NMSE both
+    single variants reach within n_iter iterations."""
+    import datagen
+    from paper_2406_06640_amd import evaluate as E
+    scans = []
+    for i, sd in enumerate(E.SIGMA_SWEEP):
+        spec = dict(datagen.CONFIGS["c1"])
+        spec.update(sigma_data=sd)
+        scans.append(datagen.make_scan(spec, [1005, 7, i]))
+    net, report = E.load_warm_start()
+    try:
+        rep = E.sweep_report(net, scans, E.SIGMA_SWEEP, n_iter)
+    finally:
+        net.close()
+    for c in rep["cases"]:
+        for k, v in list(c.items()):
+            if isinstance(v, float):
+                c[k] = round(v, 5)
+    rep["plain_sequential_wall_s"] = round(rep["plain_sequential_wall_s"], 5)
+    rep["learned_batched_wall_s"] = round(rep["learned_batched_wall_s"], 5)
+    rep["speedup"] = round(rep["speedup"], 3) if rep["speedup"] else None
+    rep["workload"] = ("far field 64x64 frames, 10x10 raster at 8 px, object 144x144, K=1, Poisson 1e5, "
+                       "sigma in {0.5,1,2,3}; batch 1; threshold per case = smallest NMSE both variants reach")
+    rep["training"] = {k: report[k] for k in ("samples", "epochs", "steps", "generation_s", "training_s",
+                                              "train_samples_per_s", "val_after")}
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +124,9 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batches", type=int, default=10)
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the time-to-NMSE comparison of the plain and the learned + batched start")
+    ap.add_argument("--warm-start-iterations", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device-to-device tensor copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -187,6 +223,9 @@ def main():
         "kernel_ms_per_step": {nm: round(ms, 4) for nm, (ms, c) in prof.items() if c},
         "final_data_error": float(errs[-1]),
     }
+    if not args.no_warm_start:
+        print("[bench] warm-start sweep (time to NMSE, plain vs learned + batched)", file=sys.stderr, flush=True)
+        out["time_to_nmse"] = warm_start_leg(args.warm_start_iterations)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, spec, args.batch, args.cpu_batches)

@@ -191,6 +191,10 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
  * err_out (host, may be NULL): [n cases][n_iter] data errors.  A case whose
  * error is non-finite is marked failed and PTYCHO_E_NUMERIC returned. */
 ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_out);
+/* enable != 0: replay each iteration of the group from a HIP graph captured on
+ * first use (an internal non-blocking stream ordered with the group's stream by
+ * events); results are bitwise those of the eager launches. */
+ptycho_status ptycho_group_set_graph(ptycho_group* g, int32_t enable);
 void ptycho_group_destroy(ptycho_group* g);
 const char* ptycho_group_last_error(const ptycho_group* g);
 

@@ -6,6 +6,11 @@ source bandwidth and the probe's aperture radius and defocus).  Six 3 x 3
 convolutions with 32 channels (zero padding 1; strides 2, 2, 2, 2, 2, 1; ReLU
 after each), a global average pool and a linear head.  Tensors are NCHW.
 
+Optionally (act_round) every stored activation is rounded after its ReLU, so
+that the ReLU decisions of the next layers are taken on the values a
+lower-precision implementation holds (its BF16 activation storage); the
+arithmetic itself stays FP64.
+
 Parameters are one flat vector, per convolution W[Co][Ci][3][3] then b[Co],
 then the head W[T][32] and b[T].  The loss is the mean squared error over the
 batch and the T outputs.  Written with plain loops over the 3 x 3 taps and
@@ -79,21 +84,32 @@ def conv_backward(x, w, stride, dy):
     return dxp[:, :, 1:h + 1, 1:wd + 1], dw, db
 
 
-def forward(theta, x, layers=LAYERS, n_out=N_OUT):
+def bf16_round(a):
+    """Round to the nearest bfloat16 value (8 significant bits, ties to even): the
+    float32 bit pattern plus 0x7FFF plus bit 16, truncated to the upper 16 bits."""
+    u = np.asarray(a, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(theta, x, layers=LAYERS, n_out=N_OUT, act_round=None):
     """Returns (outputs [n, T], cache)."""
     convs, (hw, hb) = unpack(theta, layers, n_out)
     acts = [x]
     for (w, b), (_, _, s) in zip(convs, layers):
-        acts.append(np.maximum(conv_forward(acts[-1], w, b, s), 0.0))
+        a = np.maximum(conv_forward(acts[-1], w, b, s), 0.0)
+        acts.append(act_round(a) if act_round is not None else a)
     feat = acts[-1].mean(axis=(2, 3))
     y = feat @ hw.T + hb
     return y, (acts, feat)
 
 
-def loss_and_grad(theta, x, target, layers=LAYERS, n_out=N_OUT):
-    """Mean squared error over batch and outputs, and its gradient w.r.t. theta."""
+def loss_and_grad(theta, x, target, layers=LAYERS, n_out=N_OUT, act_round=None):
+    """Mean squared error over batch and outputs, and its gradient w.r.t. theta
+    (with act_round, the gradient of the network whose activations are rounded,
+    treating the rounding as the identity)."""
     convs, (hw, hb) = unpack(theta, layers, n_out)
-    y, (acts, feat) = forward(theta, x, layers, n_out)
+    y, (acts, feat) = forward(theta, x, layers, n_out, act_round)
     nb = x.shape[0]
     diff = y - target
     loss = float(np.mean(diff ** 2))

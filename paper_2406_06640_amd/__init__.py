@@ -6,3 +6,4 @@ marshals arguments (numpy host arrays or torch device tensors) to the C ABI of
 """
 
 from .ptycho import *  # noqa: F401,F403
+from . import learned  # noqa: F401

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libptycho.so")
-SOURCES = ["kernels.hip", "runtime.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "learned_kernels.hip", "learned.cpp"]
 ARCH = os.environ.get("PTYCHO_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

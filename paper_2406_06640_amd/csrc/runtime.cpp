@@ -93,6 +93,12 @@ struct ptycho_group {
   int* d_iter = nullptr;
   std::vector<void*> allocs;
   std::string err;
+  int max_nb = 0;  // batches per iteration of the member with the most
+  // iteration replay from a captured graph
+  bool use_graph = false;
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 namespace {
@@ -1170,6 +1176,68 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
   return PTYCHO_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One iteration of every member: batches in lockstep over the tables, then
+// each table's end-of-iteration work, then the iteration counter.
+std::string enqueue_group_iteration(ptycho_group* g, hipStream_t s) {
+  for (int beta = 0; beta < g->max_nb; ++beta)
+    for (auto& tb : g->tables) {
+      std::string e = launch_batch(nullptr, tb.d_cases, tb.shape, beta, g->d_iter, s);
+      if (!e.empty()) return e;
+    }
+  for (auto& tb : g->tables) {
+    std::string e = launch_end(nullptr, tb.d_cases, tb.shape, g->d_iter, s);
+    if (!e.empty()) return e;
+  }
+  const hipError_t he = launch_iter_advance(g->d_iter, s);
+  return he == hipSuccess ? std::string() : std::string("iteration counter: ") + hipGetErrorString(he);
+}
+
+// The captured iteration reads its schedule (orders, flags, case tables) from
+// device buffers that every call refills, so one capture serves all calls as
+// long as those buffers stay where they are.
+ptycho_status build_group_graph(ptycho_group* g) {
+  if (g->gexec) return PTYCHO_OK;
+  if (!g->gstream) HIP_GTRY(g, hipStreamCreateWithFlags(&g->gstream, hipStreamNonBlocking));
+  if (!g->ev_in) HIP_GTRY(g, hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
+  if (!g->ev_out) HIP_GTRY(g, hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+  HIP_GTRY(g, hipStreamBeginCapture(g->gstream, hipStreamCaptureModeThreadLocal));
+  std::string e = enqueue_group_iteration(g, g->gstream);
+  hipGraph_t graph = nullptr;
+  hipError_t he = hipStreamEndCapture(g->gstream, &graph);
+  if (!e.empty()) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return gfail(g, PTYCHO_E_HIP, "capturing the group iteration: " + e);
+  }
+  if (he != hipSuccess) return gfail(g, PTYCHO_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+  he = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (he != hipSuccess) {
+    g->gexec = nullptr;
+    return gfail(g, PTYCHO_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+  }
+  return PTYCHO_OK;
+}
+
+void drop_group_graph(ptycho_group* g) {
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  g->gexec = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+ptycho_status ptycho_group_set_graph(ptycho_group* g, int32_t enable) {
+  if (!g) return gfail(nullptr, PTYCHO_E_INVALID, "group is NULL");
+  g->use_graph = enable != 0;
+  if (!g->use_graph) drop_group_graph(g);
+  return PTYCHO_OK;
+}
+
 ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_out) {
   if (!g) return gfail(nullptr, PTYCHO_E_INVALID, "group is NULL");
   if (n_iter < 0) return gfail(g, PTYCHO_E_INVALID, "n_iter must be >= 0");
@@ -1207,17 +1275,20 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
   for (auto& tb : g->tables)
     HIP_GTRY(g, hipMemcpyAsync(tb.d_cases, tb.h_cases, tb.members.size() * sizeof(CaseDesc), hipMemcpyHostToDevice, s));
   HIP_GTRY(g, launch_iter_set(g->d_iter, 0, s));
-  for (int it = 0; it < n_iter; ++it) {
-    for (int beta = 0; beta < max_nb; ++beta)
-      for (auto& tb : g->tables) {
-        std::string e = launch_batch(nullptr, tb.d_cases, tb.shape, beta, g->d_iter, s);
-        if (!e.empty()) return gfail(g, PTYCHO_E_HIP, e);
-      }
-    for (auto& tb : g->tables) {
-      std::string e = launch_end(nullptr, tb.d_cases, tb.shape, g->d_iter, s);
+  g->max_nb = max_nb;
+  if (g->use_graph) {
+    ptycho_status gs = build_group_graph(g);
+    if (gs != PTYCHO_OK) return gs;
+    HIP_GTRY(g, hipEventRecord(g->ev_in, s));
+    HIP_GTRY(g, hipStreamWaitEvent(g->gstream, g->ev_in, 0));
+    for (int it = 0; it < n_iter; ++it) HIP_GTRY(g, hipGraphLaunch(g->gexec, g->gstream));
+    HIP_GTRY(g, hipEventRecord(g->ev_out, g->gstream));
+    HIP_GTRY(g, hipStreamWaitEvent(s, g->ev_out, 0));
+  } else {
+    for (int it = 0; it < n_iter; ++it) {
+      std::string e = enqueue_group_iteration(g, s);
       if (!e.empty()) return gfail(g, PTYCHO_E_HIP, e);
     }
-    HIP_GTRY(g, launch_iter_advance(g->d_iter, s));
   }
   HIP_GTRY(g, hipMemcpyAsync(g->call.h_err, g->call.d_err, (size_t)n_iter * nc * sizeof(float), hipMemcpyDeviceToHost, s));
   HIP_GTRY(g, hipStreamSynchronize(s));
@@ -1239,6 +1310,11 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
 void ptycho_group_destroy(ptycho_group* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
+  if (g->gstream) (void)hipStreamSynchronize(g->gstream);
+  drop_group_graph(g);
+  if (g->gstream) (void)hipStreamDestroy(g->gstream);
+  if (g->ev_in) (void)hipEventDestroy(g->ev_in);
+  if (g->ev_out) (void)hipEventDestroy(g->ev_out);
   for (auto& tb : g->tables)
     if (tb.h_cases) (void)hipHostFree(tb.h_cases);
   for (void* p : g->allocs) (void)hipFree(p);

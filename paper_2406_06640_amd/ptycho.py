@@ -26,7 +26,7 @@ __all__ = [
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
     "ptycho_permutation", "ptycho_set_timing", "ptycho_kernel_time", "kernel_names",
     "ptycho_set_graph", "ptycho_autotune", "ptycho_dft2_bf16", "ptycho_group_create", "ptycho_group_iterate",
-    "ptycho_group_destroy", "ptycho_group_last_error", "Reconstruction", "Group",
+    "ptycho_group_destroy", "ptycho_group_last_error", "ptycho_group_set_graph", "Reconstruction", "Group",
 ]
 
 PTYCHO_OK, PTYCHO_E_INVALID, PTYCHO_E_SHAPE, PTYCHO_E_OOM = 0, -1, -2, -3
@@ -102,6 +102,7 @@ def load_library():
         "ptycho_autotune": (i32, [vp, i32, i32, P(i32)]),
         "ptycho_group_create": (i32, [P(vp), i32, P(vp)]),
         "ptycho_group_iterate": (i32, [vp, i32, fp]),
+        "ptycho_group_set_graph": (i32, [vp, i32]),
         "ptycho_group_destroy": (None, [vp]),
         "ptycho_group_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -325,6 +326,10 @@ def ptycho_group_iterate(group, n_iter, n_cases):
     return err[:, :n_iter] if n_iter else err[:, :0]
 
 
+def ptycho_group_set_graph(group, enable):
+    _gcheck(load_library().ptycho_group_set_graph(group, 1 if enable else 0), group)
+
+
 def ptycho_group_destroy(group):
     if group:
         load_library().ptycho_group_destroy(group)
@@ -339,6 +344,9 @@ class Group:
 
     def iterate(self, n_iter):
         return ptycho_group_iterate(self.g, n_iter, len(self.recs))
+
+    def set_graph(self, enable=True):
+        ptycho_group_set_graph(self.g, enable)
 
     def close(self):
         if self.g:

@@ -74,6 +74,34 @@ def test_group_matches_single_runs():
             r.close()
 
 
+def test_group_graph_replay_matches_eager_group():
+    import paper_2406_06640_amd as P
+    _announce("group of 5 uneven cases, graph replay vs eager")
+    made = [_make(i) for i in range(len(CASES))]
+    results = []
+    for graph in (False, True):
+        recs = []
+        try:
+            for s, cp in made:
+                o32, p32 = state32(s)
+                recs.append(P.Reconstruction(cp, s["intensities"], s["positions"], p32, o32))
+            with P.Group(recs) as g:
+                g.set_graph(graph)
+                errs = [g.iterate(2)]
+                _ = recs[0].object()  # eager host work between replays
+                errs.append(g.iterate(1))
+                errs.append(g.iterate(2))
+            results.append(([r.object() for r in recs], [r.probe() for r in recs], np.concatenate(errs, axis=1)))
+        finally:
+            for r in recs:
+                r.close()
+    (oe, pe, ee), (og, pg, eg) = results
+    for i in range(len(CASES)):
+        np.testing.assert_array_equal(og[i], oe[i], err_msg=f"case {i} object")
+        np.testing.assert_array_equal(pg[i], pe[i], err_msg=f"case {i} probe")
+    np.testing.assert_array_equal(eg, ee)
+
+
 @pytest.mark.parametrize("case", [0, 3, 4])
 def test_graph_replay_matches_eager(case):
     s, cp = _make(case)

@@ -49,3 +49,25 @@ def test_shapes_and_count():
     y, (acts, feat) = cnn.forward(theta, rng.standard_normal((1, 1, 128, 128)))
     assert y.shape == (1, 4)
     assert [a.shape[2] for a in acts] == [128, 64, 32, 16, 8, 4, 4]
+
+
+def test_bf16_round_values():
+    # exactly representable values are kept; ties go to the even mantissa
+    v = np.array([1.0, -2.5, 0.0, 3.140625, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9])
+    np.testing.assert_array_equal(cnn.bf16_round(v), [1.0, -2.5, 0.0, 3.140625, 1.0, 1.0 + 2.0 ** -6, 1.0])
+    r = np.random.default_rng(3).standard_normal(1000)
+    q = cnn.bf16_round(r)
+    assert np.all(np.abs(q - r) <= np.abs(r) * 2.0 ** -8)
+    np.testing.assert_array_equal(cnn.bf16_round(q), q)
+
+
+def test_rounded_activations_reduce_to_plain_network(rng):
+    layers = [(1, 3, 2), (3, 4, 2), (4, 4, 1)]
+    theta = cnn.init_params(rng, layers, 2)
+    x = rng.standard_normal((2, 1, 12, 12))
+    t = rng.standard_normal((2, 2))
+    l0, g0 = cnn.loss_and_grad(theta, x, t, layers, 2)
+    l1, g1 = cnn.loss_and_grad(theta, x, t, layers, 2, act_round=lambda a: a)
+    assert l0 == l1 and np.array_equal(g0, g1)
+    l2, g2 = cnn.loss_and_grad(theta, x, t, layers, 2, act_round=cnn.bf16_round)
+    assert abs(l2 - l0) < 1e-2 * l0
