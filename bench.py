@@ -39,7 +39,8 @@ def per_slot_bytes(name, n, k):
     return {
         "fwd_rows": 16 * nn + 8 * k * nn,            # box gather in (exit waves and V), K frames out
         "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, vertically blurred amplitude out
-        "inv_cols": 16 * k * nn + 8 * nn,            # K frames in and out, blurred amplitude + measurement in
+        "modulus_factor": 12 * nn,                   # blurred amplitude and measurement in, factor out
+        "inv_cols": 16 * k * nn + 4 * nn,            # K frames in and out, factor in
         "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
         "probe_update_constraint": 8 * k * nn,       # K probe contributions in
     }.get(name)

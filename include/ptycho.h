@@ -149,15 +149,24 @@ ptycho_status ptycho_debug_step(ptycho_ctx* ctx, const int32_t* idx, int32_t B, 
  * Not used while per-kernel timing is on. */
 ptycho_status ptycho_set_graph(ptycho_ctx* ctx, int32_t enable);
 
-/* Column-tile autotuner: times each supported column-block width of the
- * column passes on the context's first batch (`trials` timed repetitions
- * each), keeps the fastest and writes its index (0..2) to *chosen (may be
- * NULL).  The object and probe are restored afterwards.  Choices are cached
- * per (n, n_modes, batch, geometry) for the process and, when the environment
- * variable PTYCHO_TUNE_CACHE names a file, appended to it and read back by
- * later processes; force != 0 re-times a cached entry.  The object and probe
- * after any iteration are bitwise identical for every choice (the data error
- * E_t is summed in a different grouping). */
+/* Launch variants of the FFT passes: variant v (0 .. ptycho_variant_count()-1)
+ * uses column blocks of COLS/2, COLS or 2 COLS columns (v % 3; COLS is the
+ * default width for n), runs the inverse column pass with one workgroup per
+ * mode when (v / 3) & 1 and the first row pass likewise when (v / 6) & 1.
+ * Variants other than the three widths exist for n in {64, 128, 192, 256, 512}.
+ * The object and probe after any iteration are bitwise identical for every
+ * variant (the data error E_t is summed in a different grouping for other
+ * widths).  The default is variant 1. */
+int32_t ptycho_variant_count(void);
+/* Select a variant (PTYCHO_E_INVALID if it does not exist for this n). */
+ptycho_status ptycho_set_variant(ptycho_ctx* ctx, int32_t variant);
+
+/* Autotuner: times each existing launch variant on the context's first batch
+ * (`trials` timed repetitions each), keeps the fastest and writes its index to
+ * *chosen (may be NULL).  The object and probe are restored afterwards.
+ * Choices are cached per (n, n_modes, batch, geometry) for the process and,
+ * when the environment variable PTYCHO_TUNE_CACHE names a file, appended to it
+ * and read back by later processes; force != 0 re-times a cached entry. */
 ptycho_status ptycho_autotune(ptycho_ctx* ctx, int32_t trials, int32_t force, int32_t* chosen);
 
 /* Per-kernel timing with HIP events recorded on the context stream around each

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_exit(const CaseDesc* __restric
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
+  const DevBufsG d = global_bufs(bt.cs->d);
   const int n = p.n, K = p.k;
   const size_t nn = (size_t)n * n;
   const int per = (n * n + kThreads - 1) / kThreads;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_side(const CaseDesc* __restric
   __shared__ SideScratch sc;
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
-  side_job(bt.cs->p, bt.cs->d, bt.slots, bt.ns, blockIdx.x, (bt.flags & FLAG_PROBE) != 0, sc);
+  side_job(bt.cs->p, global_bufs(bt.cs->d), bt.slots, bt.ns, blockIdx.x, (bt.flags & FLAG_PROBE) != 0, sc);
 }
 
 // q[b] = sum_k |Psi_k|^2 (intensity blur) or its square root (amplitude blur).
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_modsum(const CaseDesc* __restr
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
+  const DevBufsG d = global_bufs(bt.cs->d);
   const int n = p.n, K = p.k;
   const size_t nn = (size_t)n * n;
   const int per = (n * n + kThreads - 1) / kThreads;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_blur_apply(const CaseDesc* __r
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
+  const DevBufsG d = global_bufs(bt.cs->d);
   const int n = p.n, K = p.k;
   const int tpr = n / kDftTile, tiles = tpr * tpr;
   const int b = blockIdx.x / tiles, tile = blockIdx.x % tiles;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_delta(const CaseDesc* __restri
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
+  const DevBufsG d = global_bufs(bt.cs->d);
   const int n = p.n, K = p.k;
   const size_t nn = (size_t)n * n;
   const int per = (n * n + kThreads - 1) / kThreads;

@@ -21,6 +21,7 @@
 #include "kernels.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 #include "fft_lds.hpp"
 
@@ -28,7 +29,7 @@ namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
     "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_update", "probe_update_constraint",
-    "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise"};
+    "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor"};
 
 constexpr int kThreads = 256;
 
@@ -78,6 +79,73 @@ __device__ __forceinline__ float block_max_f(float v, float* sh) {
 
 __host__ __device__ __forceinline__ int n_probe_blocks_dev(int n) { return (n * n + kThreads - 1) / kThreads; }
 
+// Pointers read from the case descriptor are generic.  Held as address-space-1
+// (global) pointers and converted back at each use, they let the compiler emit
+// global rather than flat loads and stores, which carry no ordering against
+// LDS traffic.
+#define PTY_AS1 __attribute__((address_space(1)))
+template <class T>
+struct GPtr {
+  PTY_AS1 T* p;
+  __device__ __forceinline__ operator T*() const { return (T*)p; }
+  __device__ __forceinline__ T* operator+(size_t i) const { return (T*)p + i; }
+  __device__ __forceinline__ T& operator[](size_t i) const { return ((T*)p)[i]; }
+};
+template <class T>
+__device__ __forceinline__ GPtr<T> as_global(T* ptr) {
+  return GPtr<T>{(PTY_AS1 T*)ptr};
+}
+struct DevBufsG {
+  GPtr<float2> obj, probe;
+  GPtr<float> pw;
+  GPtr<const float> amp;
+  GPtr<const int2> pos;
+  GPtr<const float2> tw, hnear;
+  GPtr<float2> X;
+  GPtr<float> q;
+  GPtr<float2> dO, nP;
+  GPtr<float> V, maxv_part, maxw_part;
+  GPtr<double> err_part;
+  GPtr<double2> cc_part, gram_part;
+  GPtr<float2> vmix;
+  GPtr<double> eig;
+};
+__device__ __forceinline__ DevBufsG global_bufs(const DevBufs& in) {
+  DevBufsG d;
+  d.obj = as_global(in.obj);
+  d.probe = as_global(in.probe);
+  d.pw = as_global(in.pw);
+  d.amp = as_global(in.amp);
+  d.pos = as_global(in.pos);
+  d.tw = as_global(in.tw);
+  d.hnear = as_global(in.hnear);
+  d.X = as_global(in.X);
+  d.q = as_global(in.q);
+  d.dO = as_global(in.dO);
+  d.nP = as_global(in.nP);
+  d.V = as_global(in.V);
+  d.maxv_part = as_global(in.maxv_part);
+  d.maxw_part = as_global(in.maxw_part);
+  d.err_part = as_global(in.err_part);
+  d.cc_part = as_global(in.cc_part);
+  d.gram_part = as_global(in.gram_part);
+  d.vmix = as_global(in.vmix);
+  d.eig = as_global(in.eig);
+  return d;
+}
+struct DebugPtrsG {
+  GPtr<float2> psi_new, n_obj;
+  GPtr<float> w_obj, factor;
+};
+__device__ __forceinline__ DebugPtrsG global_dbg(const DebugPtrs& in) {
+  DebugPtrsG g;
+  g.psi_new = as_global(in.psi_new);
+  g.n_obj = as_global(in.n_obj);
+  g.w_obj = as_global(in.w_obj);
+  g.factor = as_global(in.factor);
+  return g;
+}
+
 // The batch a block works on: case blockIdx.y of the table, batch `beta` of
 // iteration `it`.  False when the case has no such batch.
 struct Batch {
@@ -99,6 +167,11 @@ __device__ __forceinline__ bool open_batch(const CaseDesc* cases, int beta, cons
   return true;
 }
 
+template <class T, class = void>
+struct HasPre : std::false_type {};
+template <class T>
+struct HasPre<T, std::void_t<decltype(&T::pre)>> : std::true_type {};
+
 // One 1D pass over the K modes of a block's lines, with the next mode's inputs
 // gathered while the current mode is in its LDS stages.  gather(k, v) fills the
 // first-stage registers of mode k; store_for(k) returns the Store functor of mode
@@ -113,6 +186,10 @@ __device__ __forceinline__ void mode_loop(int K, float2* buf, const float2* tw, 
   gather(0, v);
   for (int k = 0; k < K; ++k) {
     auto store = store_for(k);
+    // stores whose epilogue reads other arrays fetch them here, all at once and
+    // before the transform, instead of one load per output behind each store
+    if constexpr (HasPre<decltype(store)>::value)
+      for_store_slots<N, NL, LF>([&](int s, int line, int pos) { store.pre(s, line, pos); });
     if (!NEAR) {
       fft_first<N, NL, LF, INV>(v, buf);
       if (!SINGLE && k + 1 < K) gather(k + 1, v);
@@ -135,13 +212,26 @@ __device__ __forceinline__ void mode_loop(int K, float2* buf, const float2* tw, 
 }
 
 struct SideScratch;
-__device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
+__device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots, int ns, int job, bool with_v,
                          SideScratch& sc);
 
-// Blocks with blockIdx.y >= ns do the batch's side work (see side_job).
-// Row pass 1.  Blocks past the case's slots do the batch's side work (side_job).
-template <int N, bool NEAR>
-__global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
+// Mode-parallel launches (MP) give every (slot, line block, mode) its own
+// workgroup.  Workgroups are dispatched to the 8 XCDs round-robin, so the modes
+// of one (slot, line block) are numbered g, g + 8, g + 16, ...: they land on the
+// same XCD one after another and share its L2 for the inputs they have in common.
+__device__ __forceinline__ void mp_decode(int g, int km, int& tile, int& k0) {
+  const int r = g >> 3;
+  k0 = r % km;
+  tile = (r / km) * 8 + (g & 7);
+}
+
+// Row pass 1: psi = o_b P_k and the 1D transform along x.  Serial launches walk
+// the K modes in one workgroup (blocks past the case's slots do the batch's side
+// work); MP launches take one mode each, the side blocks following the
+// `main_blocks` mode-parallel ones.
+template <int N, bool NEAR, bool MP>
+__global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it,
+                                                       int km, int main_blocks) {
   constexpr int L = Cfg<N>::ROWS;
   constexpr int LS = RegShape<N, L>::LOAD_SLOTS;
   constexpr int GX = N / L;
@@ -149,12 +239,27 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restric
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
-  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
-  if (b >= bt.ns) {
-    side_job(p, d, bt.slots, bt.ns, (b - bt.ns) * GX + bx, (bt.flags & FLAG_PROBE) != 0,
-             *reinterpret_cast<SideScratch*>(sm));
-    return;
+  const DevBufsG d = global_bufs(bt.cs->d);
+  int b, bx, k0 = 0;
+  if (MP) {
+    if ((int)blockIdx.x >= main_blocks) {
+      side_job(p, d, bt.slots, bt.ns, (int)blockIdx.x - main_blocks, (bt.flags & FLAG_PROBE) != 0,
+               *reinterpret_cast<SideScratch*>(sm));
+      return;
+    }
+    int tile;
+    mp_decode(blockIdx.x, km, tile, k0);
+    b = tile / GX;
+    bx = tile % GX;
+    if (b >= bt.ns || k0 >= p.k) return;
+  } else {
+    b = blockIdx.x / GX;
+    bx = blockIdx.x % GX;
+    if (b >= bt.ns) {
+      side_job(p, d, bt.slots, bt.ns, (b - bt.ns) * GX + bx, (bt.flags & FLAG_PROBE) != 0,
+               *reinterpret_cast<SideScratch*>(sm));
+      return;
+    }
   }
   float2* tw = sm;
   float2* hn = sm + N;
@@ -170,8 +275,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restric
   const float2* orow = d.obj + (size_t)(rc.x + y0) * W + rc.y;
   for_load_slots<N, L, false>([&](int s, int line, int pos) { o[s] = orow[line * W + pos]; });
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  const float2* p0 = d.probe + (size_t)y0 * N;
-  float2* x0 = d.X + ((size_t)b * K * N + y0) * N;
+  const float2* p0 = d.probe + ((size_t)k0 * N + y0) * N;
+  float2* x0 = d.X + (((size_t)b * K + k0) * N + y0) * N;
   auto gather = [&](int k, float2* v) {
     const float2* pk = p0 + (size_t)k * N * N;
     auto load = [&](int s, int line, int pos) { return cmul(o[s], pk[line * N + pos]); };
@@ -181,8 +286,35 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restric
     float2* out = x0 + (size_t)k * N * N;
     return [=](int s, int line, int pos, float2 v) { out[line * N + pos] = cscale(v, scale); };
   };
-  mode_loop<N, L, false, false, NEAR, false>(K, buf, tw, hn, gather, store_for);
+  mode_loop<N, L, false, false, NEAR, false>(MP ? 1 : K, buf, tw, hn, gather, store_for);
 }
+
+// Epilogue of the inverse row pass: psi' -> dpsi = psi' - o P_k; the object
+// numerator sum_k conj(P_k) dpsi_k accumulates in acc; the frame becomes
+// conj(o) dpsi_k (the probe numerator's contribution).  P_k and o are fetched
+// by pre() for every output slot before the transform.
+template <int N, int SS>
+struct InvRowsStore {
+  float2* fr;
+  const float2* pk;
+  const float2* orow;
+  float2* dbgp;
+  float2* acc;
+  int w;
+  float scale;
+  float2 pv[SS], ov[SS];
+  __device__ __forceinline__ void pre(int s, int line, int pos) {
+    pv[s] = pk[line * N + pos];
+    ov[s] = orow[line * w + pos];
+  }
+  __device__ __forceinline__ void operator()(int s, int line, int pos, float2 v) {
+    const float2 psi_new = cscale(v, scale);
+    const float2 dpsi = csub(psi_new, cmul(ov[s], pv[s]));
+    acc[s] = cadd(acc[s], cmulc(dpsi, pv[s]));  // conj(P) dpsi
+    fr[line * N + pos] = cmulc(dpsi, ov[s]);    // conj(o) dpsi
+    if (dbgp) dbgp[line * N + pos] = psi_new;
+  }
+};
 
 template <int N, bool NEAR>
 __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
@@ -195,8 +327,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restric
   const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
   if (b >= bt.ns) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
-  const DebugPtrs dbg = bt.cs->dbg;
+  const DevBufsG d = global_bufs(bt.cs->d);
+  const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
@@ -207,8 +339,6 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restric
     if (NEAR) hn[i] = d.hnear[i];
   }
   const int K = p.k, W = p.w_obj;
-  // the box rows are re-read in every mode's epilogue (cache hits) rather than
-  // held in registers, which keeps the register count of this pass down
   float2 acc[SS];
   const float2* orow = d.obj + (size_t)(rc.x + y0) * W + rc.y;
 #pragma unroll
@@ -223,18 +353,15 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restric
     fft_gather<N, L, false>(v, load);
   };
   auto store_for = [&](int k) {
-    float2* fr = x0 + (size_t)k * N * N;
-    const float2* pk = p0 + (size_t)k * N * N;
-    float2* dbgp = dbg0 ? dbg0 + (size_t)k * N * N : nullptr;
-    return [&, fr, pk, dbgp](int s, int line, int pos, float2 v) {
-      const float2 psi_new = cscale(v, scale);
-      const float2 pv = pk[line * N + pos];
-      const float2 o = orow[line * W + pos];
-      const float2 dpsi = csub(psi_new, cmul(o, pv));
-      acc[s] = cadd(acc[s], cmulc(dpsi, pv));  // conj(P) dpsi
-      fr[line * N + pos] = cmulc(dpsi, o);       // conj(o) dpsi
-      if (dbgp) dbgp[line * N + pos] = psi_new;
-    };
+    InvRowsStore<N, SS> st;
+    st.fr = x0 + (size_t)k * N * N;
+    st.pk = p0 + (size_t)k * N * N;
+    st.orow = orow;
+    st.dbgp = dbg0 ? dbg0 + (size_t)k * N * N : nullptr;
+    st.acc = acc;
+    st.w = W;
+    st.scale = scale;
+    return st;
   };
   mode_loop<N, L, false, true, NEAR, true>(K, buf, tw, hn, gather, store_for);
   float2* dO = d.dO + ((size_t)b * N + y0) * N;
@@ -264,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
   const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
   if (b >= bt.ns) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
+  const DevBufsG d = global_bufs(bt.cs->d);
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
@@ -277,6 +404,9 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
   float acc[SS];
 #pragma unroll
   for (int i = 0; i < SS; ++i) acc[i] = 0.f;
+  // blur taps in LDS: read in the store loop below without reloads behind its global stores
+  __shared__ float sgy[kMaxHalf + 1];
+  if (threadIdx.x <= kMaxHalf) sgy[threadIdx.x] = p.gy[threadIdx.x];
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   float2* f0 = d.X + (size_t)b * K * N * N + x0;
   auto gather = [&](int k, float2* v) {
@@ -301,84 +431,155 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
   __syncthreads();
   float* q = d.q + (size_t)b * N * N + x0;
   const int h = p.ks_half;
-  const float* gy = p.gy;
-  for_store_slots<N, C, true>([&](int s, int c, int y) {
-    float g = gy[0] * tile[y * TS + c];
-    for (int dy = 1; dy <= h; ++dy) g += gy[dy] * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
-    q[y * N + c] = g;
-  });
+  const float* gy = sgy;
+  // taps outermost for independent per-element chains (each element still adds
+  // its taps in the order 0, 1, ..., h)
+  float gv[SS];
+  for_store_slots<N, C, true>([&](int s, int c, int y) { gv[s] = gy[0] * tile[y * TS + c]; });
+  for (int dy = 1; dy <= h; ++dy) {
+    const float gd = gy[dy];
+    for_store_slots<N, C, true>([&](int s, int c, int y) {
+      gv[s] += gd * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
+    });
+  }
+  for_store_slots<N, C, true>([&](int s, int c, int y) { q[y * N + c] = gv[s]; });
 }
 
-// Horizontal (sigma1) half of the blur, the modulus factor of box 1 and the
-// data error, then Psi' = factor Psi and the inverse column transform.
-template <int N, bool NEAR, int C>
-__global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
-  constexpr int LS = RegShape<N, C>::LOAD_SLOTS;
-  constexpr int GX = N / C;
-  extern __shared__ float2 sm[];
+// Horizontal (sigma1) half of the blur over whole rows, the modulus factor of
+// box 1 and the data error: f = sqrt(I_meas) / (g_x (x) q + eps) (Eq. 6-7), or
+// sqrt(I_meas / (g_x (x) q + eps^2)) for the intensity blur (Eq. 2), written over
+// q in place; one data-error partial per row block.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_factor(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
+  constexpr int L = Cfg<N>::ROWS;
+  constexpr int GX = N / L;
+  constexpr int E = (L * N + kThreads - 1) / kThreads;
+  __shared__ float tile[L * N];
+  __shared__ float gx[kMaxHalf + 1];
   __shared__ double red[kThreads / 64];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
-  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  const int b = blockIdx.x / GX, by = blockIdx.x % GX;
   if (b >= bt.ns) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
-  float* dbg_factor = bt.cs->dbg.factor;
+  const DevBufsG d = global_bufs(bt.cs->d);
+  const int pat = bt.slots[b];
+  float* qb = d.q + ((size_t)b * N + by * L) * N;
+  const float* amp = d.amp + ((size_t)pat * N + by * L) * N;
+  // every input is loaded before the first store (the stores go over q)
+  float av[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    if ((L * N) % kThreads == 0 || e < L * N) {
+      tile[e] = qb[e];
+      av[j] = amp[e];
+    }
+  }
+  if (threadIdx.x <= kMaxHalf) gx[threadIdx.x] = p.gx[threadIdx.x];
+  __syncthreads();
+  const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
+  float* dbgf = dbg.factor ? dbg.factor + ((size_t)b * N + by * L) * N : nullptr;
+  const bool inten = p.blur_intensity != 0;
+  const float eps = p.eps;
+  const int h = p.ks_half;
+  double err = 0.0;
+  // taps outermost: the E elements' sums are independent chains (ILP); each
+  // element still adds its taps in the order 0, 1, ..., h
+  float gv[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    gv[j] = ((L * N) % kThreads != 0 && e >= L * N) ? 0.f : gx[0] * tile[e];
+  }
+  for (int dx = 1; dx <= h; ++dx) {
+    const float gd = gx[dx];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * kThreads;
+      if ((L * N) % kThreads != 0 && e >= L * N) continue;
+      const int c = e % N;
+      const float* row = tile + (e - c);
+      gv[j] += gd * (row[wrap(c - dx, N)] + row[wrap(c + dx, N)]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    if ((L * N) % kThreads != 0 && e >= L * N) continue;
+    const float g = gv[j];
+    const float a = av[j];
+    float ag, f;
+    if (inten) {
+      ag = sqrtf(g);
+      f = a / sqrtf(g + eps * eps);
+    } else {
+      ag = g;
+      f = a / (g + eps);
+    }
+    qb[e] = f;
+    if (dbgf) dbgf[e] = f;
+    const double dd = (double)a - (double)ag;
+    err += dd * dd;
+  }
+  const double tot = block_sum_d(err, red);
+  if (threadIdx.x == 0) d.err_part[(size_t)pat * GX + by] = tot;
+}
+
+// Psi' = factor Psi and the inverse column transform.  MP launches take one
+// mode per workgroup (see mp_decode).
+template <int N, bool NEAR, int C, bool MP>
+__global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it,
+                                                       int km) {
+  constexpr int LS = RegShape<N, C>::LOAD_SLOTS;
+  constexpr int GX = N / C;
+  extern __shared__ float2 sm[];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const DevParams& p = bt.cs->p;
+  int b, bx, k0 = 0;
+  if (MP) {
+    int tile;
+    mp_decode(blockIdx.x, km, tile, k0);
+    b = tile / GX;
+    bx = tile % GX;
+    if (b >= bt.ns || k0 >= p.k) return;
+  } else {
+    b = blockIdx.x / GX;
+    bx = blockIdx.x % GX;
+    if (b >= bt.ns) return;
+  }
+  const DevBufsG d = global_bufs(bt.cs->d);
   float2* tw = sm;
   float2* hn = sm + N;
   float2* buf = sm + 2 * N;
   const int x0 = bx * C;
-  const int pat = bt.slots[b];
   for (int i = threadIdx.x; i < N; i += kThreads) {
     tw[i] = d.tw[i];
     if (NEAR) hn[i] = d.hnear[i];
   }
-  const int h = p.ks_half;
-  const int TW = C + 2 * h;
-  float* tile = reinterpret_cast<float*>(buf);
-  const float* q = d.q + (size_t)b * N * N;
-  for (int y = threadIdx.x >> 5; y < N; y += kThreads >> 5)
-    for (int cc = threadIdx.x & 31; cc < TW; cc += 32) tile[y * TW + cc] = q[y * N + wrap(x0 - h + cc, N)];
-  __syncthreads();
   float f[LS];
-  double err = 0.0;
-  const float* amp = d.amp + (size_t)pat * N * N + x0;
-  float* dbgf = dbg_factor ? dbg_factor + (size_t)b * N * N + x0 : nullptr;
-  const bool inten = p.blur_intensity != 0;
-  const float eps = p.eps;
-  const float* gx = p.gx;
-  for_load_slots<N, C, true>([&](int s, int c, int y) {
-    const float* row = tile + y * TW + c + h;
-    float g = gx[0] * row[0];
-    for (int dx = 1; dx <= h; ++dx) g += gx[dx] * (row[-dx] + row[dx]);
-    const float a = amp[y * N + c];
-    float ag;
-    if (inten) {
-      ag = sqrtf(g);
-      f[s] = a / sqrtf(g + eps * eps);
-    } else {
-      ag = g;
-      f[s] = a / (g + eps);
-    }
-    if (dbgf) dbgf[y * N + c] = f[s];
-    const double dd = (double)a - (double)ag;
-    err += dd * dd;
-  });
-  const double tot = block_sum_d(err, red);  // also orders the tile reads before the FFT's LDS writes
-  if (threadIdx.x == 0) d.err_part[(size_t)pat * GX + bx] = tot;
+  const float* fq = d.q + (size_t)b * N * N + x0;
+  for_load_slots<N, C, true>([&](int s, int c, int y) { f[s] = fq[y * N + c]; });
   const int K = p.k;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
-  float2* f0 = d.X + (size_t)b * K * N * N + x0;
+  float2* f0 = d.X + ((size_t)b * K + k0) * N * N + x0;
   auto gather = [&](int k, float2* v) {
     const float2* fr = f0 + (size_t)k * N * N;
-    auto load = [&](int s, int c, int y) { return cscale(fr[y * N + c], f[s]); };
+    auto load = [&](int s, int c, int y) {
+      // a rounded product of its own, never fused into the first butterflies:
+      // serial and mode-parallel launches then give bitwise the same frames
+#pragma clang fp contract(off)
+      const float2 x = fr[y * N + c];
+      return make_float2(x.x * f[s], x.y * f[s]);
+    };
     fft_gather<N, C, true>(v, load);
   };
   auto store_for = [&](int k) {
     float2* fr = f0 + (size_t)k * N * N;
     return [=](int s, int c, int y, float2 v) { fr[y * N + c] = cscale(v, scale); };
   };
-  mode_loop<N, C, true, true, NEAR, true>(K, buf, tw, hn, gather, store_for);
+  mode_loop<N, C, true, true, NEAR, true>(MP ? 1 : K, buf, tw, hn, gather, store_for);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,7 +594,7 @@ struct TileList {
   int cnt[kThreads / 64];
 };
 
-__device__ __forceinline__ int tile_list(const DevBufs& d, const int* slots, int ns, int n, int r0, int c0,
+__device__ __forceinline__ int tile_list(const DevBufsG& d, const int* slots, int ns, int n, int r0, int c0,
                                          TileList& tl) {
   const int b = threadIdx.x;
   int2 rc = make_int2(0, 0);
@@ -444,7 +645,7 @@ struct SideScratch {
 // before any update of the batch): job < tiles: the maximum over one object
 // tile of W(r) = sum_b sum_k |P_k(r - r_b)|^2; next jobs (probe update only):
 // V(pix) = sum_b |o_b(pix)|^2 over one block of probe pixels and its maximum.
-__device__ void side_job(const DevParams& p, const DevBufs& d, const int* slots, int ns, int job, bool with_v,
+__device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots, int ns, int job, bool with_v,
                          SideScratch& sc) {
   const int n = p.n;
   const int tiles_x = tiles_x_of(p);
@@ -514,8 +715,8 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
-  const DebugPtrs dbg = bt.cs->dbg;
+  const DevBufsG d = global_bufs(bt.cs->d);
+  const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
   const int tiles = tiles_of(p), tiles_x = tiles_x_of(p);
   const int tile = blockIdx.x;
   if (tile >= tiles) return;
@@ -539,23 +740,47 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
     num[q] = make_float2(0.f, 0.f);
     mult[q] = 0;
   }
-  for (int i = 0; i < cnt; ++i) {
-    const int2 rc = tl.pos[i];
-    const float2* dOb = d.dO + (size_t)tl.slot[i] * nn;
-    const int xx = c0 + tx - rc.y;
+  // slots are visited in ascending order; the loads of kGather slots are issued
+  // together before their (in-order) accumulation
+  constexpr int kGather = 4;
+  const float* pw = d.pw;
+  for (int i0 = 0; i0 < cnt; i0 += kGather) {
+    float wv[kGather][kTilePix];
+    float2 nv[kGather][kTilePix];
+    bool in[kGather][kTilePix];
 #pragma unroll
-    for (int q = 0; q < kTilePix; ++q) {
-      const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
-      if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) {
-        w[q] += d.pw[yy * n + xx];
-        num[q] = cadd(num[q], dOb[yy * n + xx]);
-        ++mult[q];
+    for (int j = 0; j < kGather; ++j) {
+      const int i = i0 + j;
+      const int2 rc = i < cnt ? tl.pos[i] : make_int2(-(1 << 20), -(1 << 20));
+      const float2* dOb = d.dO + (size_t)(i < cnt ? tl.slot[i] : 0) * nn;
+      const int xx = c0 + tx - rc.y;
+#pragma unroll
+      for (int q = 0; q < kTilePix; ++q) {
+        const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
+        in[j][q] = (unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n;
+        wv[j][q] = in[j][q] ? pw[yy * n + xx] : 0.f;
+        nv[j][q] = in[j][q] ? dOb[yy * n + xx] : make_float2(0.f, 0.f);
       }
     }
+#pragma unroll
+    for (int j = 0; j < kGather; ++j)
+#pragma unroll
+      for (int q = 0; q < kTilePix; ++q)
+        if (in[j][q]) {
+          w[q] += wv[j][q];
+          num[q] = cadd(num[q], nv[j][q]);
+          ++mult[q];
+        }
   }
   const float gam = p.gamma_obj, step = p.obj_step;
   float sa = 0.f, sp = 0.f;
   const int c = c0 + tx;
+  float2 ov[kTilePix];
+#pragma unroll
+  for (int q = 0; q < kTilePix; ++q) {
+    const int r = r0 + ty + q * kTileRowsPerPass;
+    ov[q] = (mult[q] && r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
+  }
 #pragma unroll
   for (int q = 0; q < kTilePix; ++q) {
     const int r = r0 + ty + q * kTileRowsPerPass;
@@ -565,7 +790,7 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
       dbg.n_obj[oi] = num[q];
       dbg.w_obj[oi] = w[q];
     }
-    float2 o = d.obj[oi];
+    float2 o = ov[q];
     const float den = (1.0f - gam) * w[q] + gam * maxw;
     if (den > 0.f) {
       const float s = step / den;
@@ -610,7 +835,7 @@ __global__ __launch_bounds__(kThreads) void k_post(const CaseDesc* __restrict__ 
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
-  const DevBufs d = bt.cs->d;
+  const DevBufsG d = global_bufs(bt.cs->d);
   const int n = p.n, K = p.k;
   const size_t nn = (size_t)n * n;
   const bool probe = (bt.flags & FLAG_PROBE) != 0, cc = (bt.flags & FLAG_CC) != 0;
@@ -636,9 +861,10 @@ __global__ __launch_bounds__(kThreads) void k_post(const CaseDesc* __restrict__ 
       }
       for (; b < ns; ++b) s0 = cadd(s0, x[(size_t)b * st]);
       const float2 np = cadd(cadd(s0, s1), cadd(s2, s3));
-      d.nP[(size_t)k * nn + pix] = np;
-      const float den = (1.0f - p.gamma_probe) * d.V[pix] + p.gamma_probe * maxv;
+      const float vv = d.V[pix];
       float2 v = d.probe[(size_t)k * nn + pix];
+      d.nP[(size_t)k * nn + pix] = np;
+      const float den = (1.0f - p.gamma_probe) * vv + p.gamma_probe * maxv;
       if (den > 0.f) {
         const float sc = p.probe_step / den;
         v.x += sc * np.x;
@@ -721,7 +947,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const CaseDesc* __restrict__ 
   const CaseDesc* cs = cases + blockIdx.y;
   if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
   const DevParams& p = cs->p;
-  const DevBufs d = cs->d;
+  const DevBufsG d = global_bufs(cs->d);
   const int K = p.k;
   // blockIdx.x = pair (i <= j) * kGramBlocks + pixel chunk
   int pair = blockIdx.x / kGramBlocks;
@@ -757,7 +983,7 @@ __global__ void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict_
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const CaseDesc* cs = cases + blockIdx.y;
   if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
-  const DevBufs d = cs->d;
+  const DevBufsG d = global_bufs(cs->d);
   const int K = cs->p.k;
   double ar[kMaxModes][kMaxModes], ai[kMaxModes][kMaxModes];
   double vr[kMaxModes][kMaxModes], vi[kMaxModes][kMaxModes];
@@ -862,7 +1088,7 @@ __global__ void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict_
 __global__ __launch_bounds__(kThreads) void k_remix(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
   const CaseDesc* cs = cases + blockIdx.y;
   if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
-  const DevBufs d = cs->d;
+  const DevBufsG d = global_bufs(cs->d);
   const int n = cs->p.n, K = cs->p.k;
   const size_t nn = (size_t)n * n;
   const int pix = blockIdx.x * kThreads + threadIdx.x;
@@ -882,7 +1108,7 @@ __global__ __launch_bounds__(kThreads) void k_remix(const CaseDesc* __restrict__
 __global__ __launch_bounds__(kThreads) void k_err_reduce(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
   __shared__ double red[kThreads / 64];
   const CaseDesc* cs = cases + blockIdx.y;
-  const double* part = cs->d.err_part;
+  const double* part = global_bufs(cs->d).err_part;
   (void)0;
   const int count = cs->n_err_part;
   double s = 0.0;
@@ -956,9 +1182,22 @@ bool supported_n(int n) {
   MACRO(8) MACRO(16) MACRO(24) MACRO(32) MACRO(48) MACRO(64) MACRO(96) MACRO(128) MACRO(192) MACRO(256) \
   MACRO(384) MACRO(512) MACRO(768) MACRO(1024)
 
+// Column variants and mode-parallel launches are instantiated for the frame
+// sizes the autotuner explores.
+template <int N>
+struct TunedCols {
+  static constexpr bool value = N == 64 || N == 128 || N == 192 || N == 256 || N == 512;
+};
+
+// Launch variant v: column width index v % 3 (COLS/2, COLS, 2 COLS), inverse
+// column pass mode-parallel if (v / 3) & 1, first row pass mode-parallel if (v / 6) & 1.
+__host__ __device__ constexpr int var_width(int v) { return v % 3; }
+__host__ __device__ constexpr bool var_mp_cols(int v) { return ((v / 3) & 1) != 0; }
+__host__ __device__ constexpr bool var_mp_rows(int v) { return ((v / 6) & 1) != 0; }
+
 template <int N>
 static int col_width_t(int v) {
-  switch (v) {
+  switch (var_width(v)) {
     case 0: return ColW<N, 0>::C;
     case 2: return ColW<N, 2>::C;
     default: return ColW<N, 1>::C;
@@ -966,7 +1205,10 @@ static int col_width_t(int v) {
 }
 template <int N>
 static bool col_valid_t(int v) {
-  return v == 1 || (v == 0 && ColW<N, 0>::VALID) || (v == 2 && ColW<N, 2>::VALID);
+  if (v < 0 || v >= kColVariants) return false;
+  if (v >= 3 && !TunedCols<N>::value) return false;
+  const int w = var_width(v);
+  return w == 1 || (w == 0 && ColW<N, 0>::VALID) || (w == 2 && ColW<N, 2>::VALID);
 }
 
 int col_width(int n, int v) {
@@ -991,15 +1233,21 @@ bool col_variant_valid(int n, int v) {
       return false;
   }
 }
-int n_err_slots(int n, int v) { return n / col_width(n, v); }
-int max_err_slots(int n) {
-  int m = 0;
-  for (int v = 0; v < kColVariants; ++v)
-    if (col_variant_valid(n, v) && n_err_slots(n, v) > m) m = n_err_slots(n, v);
-  return m;
+int n_err_slots(int n) {
+  switch (n) {
+#define PTY_CASE(N) \
+  case N:           \
+    return N / Cfg<N>::ROWS;
+    PTY_FOR_EACH_N(PTY_CASE)
+#undef PTY_CASE
+    default:
+      return 1;
+  }
 }
 int n_obj_tiles(const DevParams& p) { return tiles_of(p); }
 int n_probe_blocks(int n) { return n_probe_blocks_dev(n); }
+
+static int mp_blocks(int tiles, int km) { return ((tiles + 7) / 8) * 8 * km; }
 
 template <int N, bool NEAR>
 static hipError_t fwd_rows_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
@@ -1007,9 +1255,17 @@ static hipError_t fwd_rows_t(const CaseDesc* cases, const TableShape& t, int bet
   size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
   if (sh < sizeof(SideScratch)) sh = sizeof(SideScratch);
   const int gx = N / L;
+  if constexpr (TunedCols<N>::value) {
+    if (var_mp_rows(t.col_variant)) {
+      const int main = mp_blocks(gx * t.max_batch, t.max_k);
+      hipLaunchKernelGGL((k_fwd_rows<N, NEAR, true>), dim3(main + t.max_side_jobs, t.n_cases), dim3(kThreads), sh, s,
+                         cases, beta, it, t.max_k, main);
+      return hipGetLastError();
+    }
+  }
   const int side_rows = (t.max_side_jobs + gx - 1) / gx;
-  hipLaunchKernelGGL((k_fwd_rows<N, NEAR>), dim3(gx * (t.max_batch + side_rows), t.n_cases), dim3(kThreads), sh, s,
-                     cases, beta, it);
+  hipLaunchKernelGGL((k_fwd_rows<N, NEAR, false>), dim3(gx * (t.max_batch + side_rows), t.n_cases), dim3(kThreads),
+                     sh, s, cases, beta, it, 1, 0);
   return hipGetLastError();
 }
 template <int N, bool NEAR>
@@ -1028,34 +1284,40 @@ static hipError_t fwd_cols_v(const CaseDesc* cases, const TableShape& t, int bet
                      cases, beta, it);
   return hipGetLastError();
 }
+template <int N>
+static hipError_t factor_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL((k_factor<N>), dim3((N / Cfg<N>::ROWS) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases,
+                     beta, it);
+  return hipGetLastError();
+}
 template <int N, bool NEAR, int V>
 static hipError_t inv_cols_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int C = ColW<N, V>::C;
-  const size_t fft = sizeof(float2) * Frame<N, C, true>::ELEMS;
-  const size_t halo = sizeof(float) * (size_t)N * (C + 2 * kMaxHalf);
-  const size_t sh = sizeof(float2) * 2 * N + (fft > halo ? fft : halo);
-  hipLaunchKernelGGL((k_inv_cols<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
-                     cases, beta, it);
+  const size_t sh = sizeof(float2) * (2 * N + Frame<N, C, true>::ELEMS);
+  if constexpr (TunedCols<N>::value) {
+    if (var_mp_cols(t.col_variant)) {
+      hipLaunchKernelGGL((k_inv_cols<N, NEAR, C, true>), dim3(mp_blocks((N / C) * t.max_batch, t.max_k), t.n_cases),
+                         dim3(kThreads), sh, s, cases, beta, it, t.max_k);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_inv_cols<N, NEAR, C, false>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
+                     cases, beta, it, 1);
   return hipGetLastError();
 }
-// Column variants are instantiated for the frame sizes the autotuner explores.
-template <int N>
-struct TunedCols {
-  static constexpr bool value = N == 64 || N == 128 || N == 192 || N == 256 || N == 512;
-};
 template <int N, bool NEAR>
 static hipError_t fwd_cols_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   if constexpr (TunedCols<N>::value) {
-    if (t.col_variant == 0) return fwd_cols_v<N, NEAR, 0>(cases, t, beta, it, s);
-    if (t.col_variant == 2) return fwd_cols_v<N, NEAR, 2>(cases, t, beta, it, s);
+    if (var_width(t.col_variant) == 0) return fwd_cols_v<N, NEAR, 0>(cases, t, beta, it, s);
+    if (var_width(t.col_variant) == 2) return fwd_cols_v<N, NEAR, 2>(cases, t, beta, it, s);
   }
   return fwd_cols_v<N, NEAR, 1>(cases, t, beta, it, s);
 }
 template <int N, bool NEAR>
 static hipError_t inv_cols_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   if constexpr (TunedCols<N>::value) {
-    if (t.col_variant == 0) return inv_cols_v<N, NEAR, 0>(cases, t, beta, it, s);
-    if (t.col_variant == 2) return inv_cols_v<N, NEAR, 2>(cases, t, beta, it, s);
+    if (var_width(t.col_variant) == 0) return inv_cols_v<N, NEAR, 0>(cases, t, beta, it, s);
+    if (var_width(t.col_variant) == 2) return inv_cols_v<N, NEAR, 2>(cases, t, beta, it, s);
   }
   return inv_cols_v<N, NEAR, 1>(cases, t, beta, it, s);
 }
@@ -1080,6 +1342,10 @@ static hipError_t inv_cols_t(const CaseDesc* cases, const TableShape& t, int bet
 #define PTY_CASE_inv_cols(N) \
   case N:                    \
     return t.near_field ? inv_cols_t<N, true>(cases, t, beta, it, s) : inv_cols_t<N, false>(cases, t, beta, it, s);
+#define PTY_CASE_factor(N) \
+  case N:                  \
+    return factor_t<N>(cases, t, beta, it, s);
+PTY_DEFINE_LAUNCH(factor)
 PTY_DEFINE_LAUNCH(fwd_rows)
 PTY_DEFINE_LAUNCH(inv_rows)
 PTY_DEFINE_LAUNCH(fwd_cols)

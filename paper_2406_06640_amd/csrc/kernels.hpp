@@ -20,7 +20,9 @@ constexpr int kMaxModes = 16;
 constexpr int kMaxBatch = 256;
 constexpr int kObjTile = 32;     // object tile side for the gather/update kernels
 constexpr int kGramBlocks = 16;  // pixel chunks of the Gram matrix reduction
-constexpr int kColVariants = 3;  // column-tile widths tried by the autotuner: COLS/2, COLS, 2 COLS
+// launch variants tried by the autotuner: column-tile width COLS/2, COLS or 2 COLS (v % 3),
+// mode-parallel inverse column pass ((v / 3) & 1), mode-parallel first row pass ((v / 6) & 1)
+constexpr int kColVariants = 12;
 
 // Per-iteration flags of a case.
 enum : int { FLAG_PROBE = 1, FLAG_CC = 2, FLAG_ORTHO = 4 };
@@ -92,7 +94,7 @@ struct TableShape {
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_POST, KC_GRAM, KC_EIG, KC_REMIX,
-  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_COUNT
+  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -101,6 +103,7 @@ extern const char* const kKernelNames[KC_COUNT];
 // graph can be replayed unchanged).
 hipError_t launch_fwd_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_fwd_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_factor(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
@@ -132,8 +135,7 @@ hipError_t launch_dft_blur_apply(const CaseDesc* cases, const TableShape& t, int
 hipError_t launch_dft_delta(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 
 int n_obj_tiles(const DevParams& p);
-int n_err_slots(int n, int col_variant);  // data-error partials per position (one per column block)
-int max_err_slots(int n);                 // over all column variants
+int n_err_slots(int n);  // data-error partials per position (one per row block of the factor pass)
 int n_probe_blocks(int n);
 int col_width(int n, int col_variant);    // columns per column block
 bool col_variant_valid(int n, int col_variant);

@@ -301,6 +301,7 @@ std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape
                          hipStream_t s) {
   LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
   LAUNCH(tc, KC_FWD_COLS, s, launch_fwd_cols(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_FACTOR, s, launch_factor(cases, sh, beta, it, s));
   LAUNCH(tc, KC_INV_COLS, s, launch_inv_cols(cases, sh, beta, it, s));
   LAUNCH(tc, KC_INV_ROWS, s, launch_inv_rows(cases, sh, beta, it, s));
   LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
@@ -356,7 +357,7 @@ void fill_case(const ptycho_ctx* c, CaseDesc& cd, const int* order, const int* f
   cd.n_pos = c->prm.n_pos;
   cd.batch = c->prm.batch;
   cd.n_batches = n_batches_of(c->prm);
-  cd.n_err_part = c->prm.n_pos * (c->prm.dft_bf16 ? dft_err_slots(c->prm.n) : n_err_slots(c->prm.n, c->col_variant));
+  cd.n_err_part = c->prm.n_pos * (c->prm.dft_bf16 ? dft_err_slots(c->prm.n) : n_err_slots(c->prm.n));
 }
 
 TableShape single_shape(const ptycho_ctx* c, int max_batch) {
@@ -657,7 +658,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   double *errp, *eig;
   double2 *ccp, *gramp;
   const int nobjt = n_obj_tiles(dp);
-  const int nbt = std::max(max_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
+  const int nbt = std::max(n_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
   ptycho_status st = PTYCHO_OK;
   if ((st = dev_alloc(c, &obj, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &probe, K * nn)) ||
       (st = dev_alloc(c, &pw, nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
@@ -844,6 +845,18 @@ ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order
       return fail(c, PTYCHO_E_NUMERIC,
                   "non-finite data error at iteration " + std::to_string(c->t - n_iter + 1 + i));
     }
+  return PTYCHO_OK;
+}
+
+int32_t ptycho_variant_count(void) { return kColVariants; }
+
+ptycho_status ptycho_set_variant(ptycho_ctx* c, int32_t variant) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (!col_variant_valid(c->prm.n, variant))
+    return fail(c, PTYCHO_E_INVALID, "launch variant " + std::to_string(variant) + " does not exist for n = " +
+                                         std::to_string(c->prm.n));
+  if (variant != c->col_variant) drop_graph(c);
+  c->col_variant = variant;
   return PTYCHO_OK;
 }
 
@@ -1267,7 +1280,7 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
       const int i = tb.members[m];
       fill_case(g->ctx[i], tb.h_cases[m], g->call.d_order + off[i], g->call.d_flags + (size_t)i * n_iter,
                 g->call.d_err + (size_t)i * n_iter);
-      tb.h_cases[m].n_err_part = g->ctx[i]->prm.n_pos * n_err_slots(tb.shape.n, tb.shape.col_variant);
+      tb.h_cases[m].n_err_part = g->ctx[i]->prm.n_pos * n_err_slots(tb.shape.n);
     }
   HIP_GTRY(g, hipMemcpyAsync(g->call.d_order, g->call.h_order, off[nc] * sizeof(int), hipMemcpyHostToDevice, s));
   HIP_GTRY(g, hipMemcpyAsync(g->call.d_flags, g->call.h_flags, (size_t)n_iter * nc * sizeof(int),

@@ -25,7 +25,7 @@ __all__ = [
     "ptycho_init", "ptycho_iterate", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
     "ptycho_permutation", "ptycho_set_timing", "ptycho_kernel_time", "kernel_names",
-    "ptycho_set_graph", "ptycho_autotune", "ptycho_dft2_bf16", "ptycho_group_create", "ptycho_group_iterate",
+    "ptycho_set_graph", "ptycho_set_variant", "ptycho_variant_count", "ptycho_autotune", "ptycho_dft2_bf16", "ptycho_group_create", "ptycho_group_iterate",
     "ptycho_group_destroy", "ptycho_group_last_error", "ptycho_group_set_graph", "Reconstruction", "Group",
 ]
 
@@ -98,6 +98,8 @@ def load_library():
         "ptycho_last_error": (ctypes.c_char_p, [vp]),
         "ptycho_permutation": (i32, [u64, i32, i32, fp]),
         "ptycho_set_graph": (i32, [vp, i32]),
+        "ptycho_set_variant": (i32, [vp, i32]),
+        "ptycho_variant_count": (i32, []),
         "ptycho_dft2_bf16": (i32, [fp, i32, i32, i32, vp]),
         "ptycho_autotune": (i32, [vp, i32, i32, P(i32)]),
         "ptycho_group_create": (i32, [P(vp), i32, P(vp)]),
@@ -292,6 +294,14 @@ def ptycho_dft2_bf16(frames, inverse=False, stream=None):
     return frames
 
 
+def ptycho_variant_count():
+    return int(load_library().ptycho_variant_count())
+
+
+def ptycho_set_variant(ctx, variant):
+    _check(load_library().ptycho_set_variant(ctx, int(variant)), ctx)
+
+
 def ptycho_set_graph(ctx, enable):
     _check(load_library().ptycho_set_graph(ctx, 1 if enable else 0), ctx)
 
@@ -391,6 +401,9 @@ class Reconstruction:
 
     def set_graph(self, enable=True):
         ptycho_set_graph(self.ctx, enable)
+
+    def set_variant(self, variant):
+        ptycho_set_variant(self.ctx, variant)
 
     def autotune(self, trials=3, force=False):
         return ptycho_autotune(self.ctx, trials, force)
