@@ -117,6 +117,107 @@ def warm_start_leg(n_iter):
     return rep
 
 
+def c4_leg(iters):
+    """The 64-case batched workload (N in {64,128,192,256}, 100-2500 positions, 1-8 modes, batch 32,
+    seeds [1004, i]; patterns made on the GPU): every case alone (autotuned, graph replay) against
+    all cases as one group (graph replay), same final states required bitwise; and the BF16
+    matrix-core DFT path on the cases whose N it supports, with its object error against the
+    FP32 FFT path after the same iterations."""
+    import torch
+    import datagen
+    from datagen import gpu_synth
+    import paper_2406_06640_amd as P
+    t0 = time.time()
+    cases = []
+    for i in range(64):
+        sp = datagen.random_case_spec(i)
+        cases.append((sp, gpu_synth.make_scan(sp, sp["seed_key"])))
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    print(f"[bench] c4 generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    def make(sp, s, dft=False):
+        h, w = s["obj0"].shape
+        cp = P.default_params(n=s["n"], n_modes=s["k"], n_pos=len(s["positions"]), obj_h=h, obj_w=w,
+                              sigma1=sp["sigma"], sigma2=sp["sigma"], batch=sp["batch"], seed=1,
+                              dft_bf16=1 if dft else 0)
+        cp.cc_start, cp.cc_end = 1, 0
+        pos = torch.from_numpy(s["positions"]).cuda()
+        p0 = torch.from_numpy(s["probe0"].astype(np.complex64)).cuda()
+        o0 = torch.from_numpy(s["obj0"].astype(np.complex64)).cuda()
+        return P.Reconstruction(cp, s["intensities_dev"], pos, p0, o0, mem_kind=P.PTYCHO_MEM_DEVICE)
+
+    updates = sum(len(s["positions"]) * s["k"] for _, s in cases)
+    singles = [make(sp, s) for sp, s in cases]
+    variants = [r.autotune(trials=2) for r in singles]
+    for r in singles:
+        r.set_graph(True)
+        r.iterate(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in singles:
+        r.iterate(iters)
+    torch.cuda.synchronize()
+    wall_single = time.perf_counter() - t0
+    grouped = [make(sp, s) for sp, s in cases]
+    with P.Group(grouped) as g:
+        g.set_graph(True)
+        g.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.iterate(iters)
+        torch.cuda.synchronize()
+        wall_group = time.perf_counter() - t0
+    same = all(np.array_equal(a.object(), b.object()) and np.array_equal(a.probe(), b.probe())
+               for a, b in zip(singles, grouped))
+    for r in grouped:
+        r.close()
+    dft_rows, wall_dft, wall_fft_sub, upd_sub = [], 0.0, 0.0, 0
+    for (sp, s), ref in zip(cases, singles):
+        if s["n"] not in (64, 128, 256):
+            continue
+        with make(sp, s, dft=True) as r:
+            r.iterate(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.iterate(iters)
+            torch.cuda.synchronize()
+            wall_dft += time.perf_counter() - t0
+            o = r.object().astype(np.complex128)
+        o_ref = ref.object().astype(np.complex128)
+        dft_rows.append({"n": s["n"], "k": s["k"], "positions": len(s["positions"]),
+                         "object_rel_l2_vs_fp32": float(np.linalg.norm(o - o_ref) / np.linalg.norm(o_ref))})
+        upd_sub += len(s["positions"]) * s["k"]
+    # the FP32 path on the same subset (eager launches like the DFT runs), for the comparison
+    for (sp, s), r in zip(cases, singles):
+        if s["n"] in (64, 128, 256):
+            r.set_graph(False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.iterate(iters)
+            torch.cuda.synchronize()
+            wall_fft_sub += time.perf_counter() - t0
+    for r in singles:
+        r.close()
+    errs = [row["object_rel_l2_vs_fp32"] for row in dft_rows]
+    return {
+        "workload": "64 far-field cases, N in {64,128,192,256}, 100-2500 positions, K 1-8, batch 32, "
+                    "Poisson 1e5, sigma 1; seeds [1004, i]",
+        "iterations": iters, "mode_pattern_updates_per_iteration": updates, "generation_s": round(gen_s, 2),
+        "one_by_one": {"wall_s": round(wall_single, 4), "updates_per_s": round(updates * iters / wall_single, 1)},
+        "group": {"wall_s": round(wall_group, 4), "updates_per_s": round(updates * iters / wall_group, 1),
+                  "bitwise_equal_to_one_by_one": bool(same)},
+        "autotuned_variants": variants,
+        "dft_bf16": {"cases": len(dft_rows), "wall_s": round(wall_dft, 4),
+                     "updates_per_s": round(upd_sub * iters / wall_dft, 1) if wall_dft else None,
+                     "fp32_fft_updates_per_s_same_cases": round(upd_sub * iters / wall_fft_sub, 1)
+                     if wall_fft_sub else None,
+                     "object_rel_l2_vs_fp32_max": max(errs) if errs else None,
+                     "object_rel_l2_vs_fp32_median": float(np.median(errs)) if errs else None,
+                     "per_case": dft_rows},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +229,10 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the time-to-NMSE comparison of the plain and the learned + batched start")
     ap.add_argument("--warm-start-iterations", type=int, default=30)
+    ap.add_argument("--c4", action="store_true",
+                    help="also run the 64-case batched workload: group launch vs the cases one by one, "
+                         "and the BF16 matrix-core DFT path")
+    ap.add_argument("--c4-iterations", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device-to-device tensor copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -227,6 +332,9 @@ def main():
     if not args.no_warm_start:
         print("[bench] warm-start sweep (time to NMSE, plain vs learned + batched)", file=sys.stderr, flush=True)
         out["time_to_nmse"] = warm_start_leg(args.warm_start_iterations)
+    if args.c4:
+        print("[bench] 64-case batched workload", file=sys.stderr, flush=True)
+        out["c4"] = c4_leg(args.c4_iterations)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, spec, args.batch, args.cpu_batches)

@@ -15,13 +15,21 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
+// No implicit multiply-add fusion in any code that includes this header: the
+// fused operations are the explicit fmaf calls below, so every instantiation
+// of a kernel (tile widths, serial or mode-parallel launches, groups) rounds
+// exactly alike and their results agree bitwise.
+#pragma clang fp contract(off)
+
 namespace pty {
 
 __host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __host__ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
 __host__ __device__ __forceinline__ float2 conjc(float2 a) { return make_float2(a.x, -a.y); }
 __host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

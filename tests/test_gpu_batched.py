@@ -141,6 +141,33 @@ def test_every_launch_variant_gives_the_same_result(case):
     assert len(ran) >= 8
 
 
+@pytest.mark.parametrize("n,k", [(128, 3), (192, 2), (256, 1), (256, 4)])
+def test_launch_variants_agree_for_larger_frames(n, k):
+    """Every launch variant of the larger frame sizes, one batch step, bitwise."""
+    import paper_2406_06640_amd as P
+    s = make_case(n=n, k=k, obj=(n + 64, n + 64), n_side=3, step=24, radius=n // 4, seed=40 + n + k)
+    cp, _ = params_pair(s, batch=5, cc_start=1, cc_end=2, seed=3)
+    _announce(f"launch variants n={n} K={k}")
+    o32, p32 = state32(s)
+    ref, ran = None, []
+    for v in range(P.ptycho_variant_count()):
+        with P.Reconstruction(cp, s["intensities"], s["positions"], p32, o32) as r:
+            try:
+                r.set_variant(v)
+            except P.PtychoError:
+                continue
+            r.iterate(1)
+            got = (r.object(), r.probe())
+        ran.append(v)
+        if ref is None:
+            ref = got
+        else:
+            np.testing.assert_array_equal(got[0], ref[0], err_msg=f"variant {v} object")
+            np.testing.assert_array_equal(got[1], ref[1], err_msg=f"variant {v} probe")
+    print(f"variants run: {ran}", flush=True)
+    assert len(ran) >= 8
+
+
 def test_autotune_choice_keeps_results():
     """Every column-tile variant gives the same object and probe."""
     import paper_2406_06640_amd as P
