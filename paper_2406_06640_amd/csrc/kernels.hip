@@ -292,21 +292,17 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restric
 // Epilogue of the inverse row pass: psi' -> dpsi = psi' - o P_k; the object
 // numerator sum_k conj(P_k) dpsi_k accumulates in acc; the frame becomes
 // conj(o) dpsi_k (the probe numerator's contribution).  P_k and o are fetched
-// by pre() for every output slot before the transform.
+// (P_k by pre(), the box once per workgroup) for every output slot before the transform.
 template <int N, int SS>
 struct InvRowsStore {
   float2* fr;
   const float2* pk;
-  const float2* orow;
+  const float2* ov;  // the box values of the thread's output slots (registers)
   float2* dbgp;
   float2* acc;
-  int w;
   float scale;
-  float2 pv[SS], ov[SS];
-  __device__ __forceinline__ void pre(int s, int line, int pos) {
-    pv[s] = pk[line * N + pos];
-    ov[s] = orow[line * w + pos];
-  }
+  float2 pv[SS];
+  __device__ __forceinline__ void pre(int s, int line, int pos) { pv[s] = pk[line * N + pos]; }
   __device__ __forceinline__ void operator()(int s, int line, int pos, float2 v) {
     const float2 psi_new = cscale(v, scale);
     const float2 dpsi = csub(psi_new, cmul(ov[s], pv[s]));
@@ -343,6 +339,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restric
   const float2* orow = d.obj + (size_t)(rc.x + y0) * W + rc.y;
 #pragma unroll
   for (int i = 0; i < SS; ++i) acc[i] = make_float2(0.f, 0.f);
+  float2 ob[SS];
+  for_store_slots<N, L, false>([&](int s, int line, int pos) { ob[s] = orow[line * W + pos]; });
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   float2* x0 = d.X + ((size_t)b * K * N + y0) * N;
   const float2* p0 = d.probe + (size_t)y0 * N;
@@ -356,10 +354,9 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restric
     InvRowsStore<N, SS> st;
     st.fr = x0 + (size_t)k * N * N;
     st.pk = p0 + (size_t)k * N * N;
-    st.orow = orow;
+    st.ov = ob;
     st.dbgp = dbg0 ? dbg0 + (size_t)k * N * N : nullptr;
     st.acc = acc;
-    st.w = W;
     st.scale = scale;
     return st;
   };
@@ -661,14 +658,25 @@ __device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots
     float w[kTilePix];
 #pragma unroll
     for (int q = 0; q < kTilePix; ++q) w[q] = 0.f;
-    for (int i = 0; i < cnt; ++i) {
-      const int2 rc = sc.tl.pos[i];
-      const int xx = c0 + tx - rc.y;
+    const float* pw = d.pw;
+    for (int i0 = 0; i0 < cnt; i0 += 4) {  // four slots' loads in flight, summed in slot order
+      float wv[4][kTilePix];
 #pragma unroll
-      for (int q = 0; q < kTilePix; ++q) {
-        const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
-        if ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) w[q] += d.pw[yy * n + xx];
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + j;
+        const int2 rc = i < cnt ? sc.tl.pos[i] : make_int2(-(1 << 20), -(1 << 20));
+        const int xx = c0 + tx - rc.y;
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q) {
+          const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
+          wv[j][q] = ((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n) ? pw[yy * n + xx] : -1.f;
+        }
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q)
+          if (wv[j][q] >= 0.f) w[q] += wv[j][q];
     }
     float m = 0.f;
 #pragma unroll
@@ -687,6 +695,17 @@ __device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots
     const int y = pix / n, x = pix - y * n;
     float v0 = 0.f, v1 = 0.f;
     int b = 0;
+    const float2* ob = d.obj;
+    for (; b + 8 <= ns; b += 8) {  // eight boxes' loads in flight; v0 sums even, v1 odd slots in order
+      float2 o[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) o[u] = ob[(size_t)(sc.bp[b + u].x + y) * p.w_obj + sc.bp[b + u].y + x];
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        v0 += o[u].x * o[u].x + o[u].y * o[u].y;
+        v1 += o[u + 1].x * o[u + 1].x + o[u + 1].y * o[u + 1].y;
+      }
+    }
     for (; b + 2 <= ns; b += 2) {
       const float2 o0 = d.obj[(size_t)(sc.bp[b].x + y) * p.w_obj + sc.bp[b].y + x];
       const float2 o1 = d.obj[(size_t)(sc.bp[b + 1].x + y) * p.w_obj + sc.bp[b + 1].y + x];
@@ -1109,10 +1128,17 @@ __global__ __launch_bounds__(kThreads) void k_err_reduce(const CaseDesc* __restr
   __shared__ double red[kThreads / 64];
   const CaseDesc* cs = cases + blockIdx.y;
   const double* part = global_bufs(cs->d).err_part;
-  (void)0;
   const int count = cs->n_err_part;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < count; i += kThreads) s += part[i];
+  // eight independent partial sums per thread (eight loads in flight), combined in a fixed order
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < count; i += 8 * kThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = i + u * kThreads;
+      if (j < count) acc[u] += part[j];
+    }
+  }
+  double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   s = block_sum_d(s, red);
   if (threadIdx.x == 0) cs->err_out[*it_ptr] = (float)(s * cs->inv_denom);
 }
