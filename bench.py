@@ -139,6 +139,77 @@ def warm_start_leg(n_iter):
     return rep
 
 
+def _time_iterations(P, torch, s, cp, steps, graph=True, autotune=True):
+    """ms per iteration of one context over `steps` timed iterations (inputs in HBM, one warm-up)."""
+    inten = torch.from_numpy(s["intensities"]).cuda()
+    pos = torch.from_numpy(s["positions"]).cuda()
+    p0 = torch.from_numpy(s["probe0"].astype(np.complex64)).cuda()
+    o0 = torch.from_numpy(s["obj0"].astype(np.complex64)).cuda()
+    with P.Reconstruction(cp, inten, pos, p0, o0, mem_kind=P.PTYCHO_MEM_DEVICE) as r:
+        variant = r.autotune(trials=2) if autotune else None
+        r.set_graph(graph)
+        r.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs = r.iterate(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    return 1e3 * wall / steps, variant, float(errs[-1])
+
+
+def c3_leg(steps=5):
+    """Near field: object 1536^2, frames 512^2, 15 x 15 positions at 60 +- 10 px, K = 8, sigma 1.5, B = 8."""
+    import torch
+    import datagen
+    import paper_2406_06640_amd as P
+    spec = datagen.CONFIGS["c3"]
+    t0 = time.time()
+    s = datagen.make_scan(spec, 1003)
+    gen = time.time() - t0
+    cp = make_params(P, s, spec, spec["batch"])
+    cp.fresnel_px = float(s["fresnel_px"])
+    ms, variant, err = _time_iterations(P, torch, s, cp, steps)
+    n_pos, k = len(s["positions"]), s["k"]
+    return {"workload": "near field, object 1536x1536, frames 512x512, 15x15 positions at 60+-10 px, K=8, "
+                        "sigma 1.5, Poisson 1e6; pc-ePIE batch 8, constraint on every iteration",
+            "ms_per_iteration": round(ms, 3), "updates_per_s": round(n_pos * k * 1e3 / ms, 1),
+            "variant": variant, "steps": steps, "generation_s": round(gen, 1), "final_data_error": err}
+
+
+def paper_shapes_leg(steps=5):
+    """The paper's scans (100 patterns of 1024^2, one mode): far field at a 7 px step, near field at
+    3 px with F_px = 4.13e-3; sequential updates (batch 1, as the paper's loop) and batch 10."""
+    import torch
+    import datagen
+    import paper_2406_06640_amd as P
+    out = {}
+    for name, geometry, step, paper_ms in (("far", 0, 7, 452.2), ("near", 1, 3, 640.0)):
+        n = 1024
+        extent = 9 * step + n + 2
+        side = int(np.ceil(extent / 16.0) * 16)
+        spec = dict(datagen.CONFIGS["c1"])
+        spec.update(geometry=geometry, obj=(side, side), n=n, n_side=10, step=step, jitter=1, k=1,
+                    powers=(1.0,), radius=n // 4, defocus=1.0 if geometry == 0 else 0.0, sigma_data=1.0,
+                    counts=1e6, fresnel_px=4.13e-3 if geometry == 1 else 0.0, sigma=1.0, batch=1)
+        t0 = time.time()
+        s = datagen.make_scan(spec, [1006, geometry])
+        gen = time.time() - t0
+        row = {"generation_s": round(gen, 1), "paper_ms_per_iteration": paper_ms}
+        for b in (1, 10):
+            cp = make_params(P, s, spec, b)
+            cp.geometry = geometry
+            cp.fresnel_px = float(spec["fresnel_px"])
+            cp.sigma1 = cp.sigma2 = 1.0
+            ms, variant, _ = _time_iterations(P, torch, s, cp, steps)
+            row[f"ms_per_iteration_batch{b}"] = round(ms, 3)
+        row["speedup_vs_paper_batch1"] = round(paper_ms / row["ms_per_iteration_batch1"], 1)
+        out[name] = row
+    out["workload"] = ("100 patterns of 1024x1024 (10x10 raster), one mode, sigma 1, 11x11 blur, constraint on; "
+                       "far field step 7 px, near field step 3 px with F_px 4.13e-3; the paper's times are "
+                       "for a TITAN Xp (ePIE-family code, precision not stated)")
+    return out
+
+
 def c4_leg(iters):
     """The 64-case batched workload (N in {64,128,192,256}, 100-2500 positions, 1-8 modes, batch 32,
     seeds [1004, i]; patterns made on the GPU): every case alone (autotuned, graph replay) against
@@ -255,6 +326,10 @@ def main():
                     help="also run the 64-case batched workload: group launch vs the cases one by one, "
                          "and the BF16 matrix-core DFT path")
     ap.add_argument("--c4-iterations", type=int, default=3)
+    ap.add_argument("--c3", action="store_true", help="also time the near-field 1536^2 / 512^2 / K=8 workload")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="also time the paper's own scan shapes (100 patterns of 1024^2, one mode, far and near "
+                         "field) for comparison with its per-iteration times")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device-to-device tensor copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -354,6 +429,12 @@ def main():
     if not args.no_warm_start:
         print("[bench] warm-start sweep (time to NMSE, plain vs learned + batched)", file=sys.stderr, flush=True)
         out["time_to_nmse"] = warm_start_leg(args.warm_start_iterations)
+    if args.c3:
+        print("[bench] near-field workload", file=sys.stderr, flush=True)
+        out["c3"] = c3_leg()
+    if args.paper_shapes:
+        print("[bench] paper-shape scans", file=sys.stderr, flush=True)
+        out["paper_shapes"] = paper_shapes_leg()
     if args.c4:
         print("[bench] 64-case batched workload", file=sys.stderr, flush=True)
         out["c4"] = c4_leg(args.c4_iterations)

@@ -997,56 +997,71 @@ __global__ __launch_bounds__(kThreads) void k_gram(const CaseDesc* __restrict__ 
 }
 
 // Hermitian eigendecomposition by cyclic complex Jacobi rotations (double),
-// one thread; K <= 16.
-__global__ void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// K <= 16.  One wave: the matrices live in LDS; every lane derives the same
+// rotation from the same LDS values, then lane m updates entry m of the two
+// rotated columns (A and the eigenvectors), and after a barrier entry m of the
+// two rotated rows -- element by element the serial sequence.
+__global__ __launch_bounds__(64) void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
+  __shared__ double ar[kMaxModes][kMaxModes], ai[kMaxModes][kMaxModes];
+  __shared__ double vr[kMaxModes][kMaxModes], vi[kMaxModes][kMaxModes];
+  __shared__ int stop;
+  if (blockIdx.x != 0) return;
   const CaseDesc* cs = cases + blockIdx.y;
   if (!(cs->flags[*it_ptr] & FLAG_ORTHO)) return;
   const DevBufsG d = global_bufs(cs->d);
   const int K = cs->p.k;
-  double ar[kMaxModes][kMaxModes], ai[kMaxModes][kMaxModes];
-  double vr[kMaxModes][kMaxModes], vi[kMaxModes][kMaxModes];
-  int pair = 0;
-  for (int i = 0; i < K; ++i)
-    for (int j = i; j < K; ++j, ++pair) {
-      double sr = 0.0, si = 0.0;
-      for (int c = 0; c < kGramBlocks; ++c) {
-        sr += d.gram_part[(size_t)pair * kGramBlocks + c].x;
-        si += d.gram_part[(size_t)pair * kGramBlocks + c].y;
+  const int m = threadIdx.x;
+  if (m == 0) {
+    int pair = 0;
+    for (int i = 0; i < K; ++i)
+      for (int j = i; j < K; ++j, ++pair) {
+        double sr = 0.0, si = 0.0;
+        for (int c = 0; c < kGramBlocks; ++c) {
+          sr += d.gram_part[(size_t)pair * kGramBlocks + c].x;
+          si += d.gram_part[(size_t)pair * kGramBlocks + c].y;
+        }
+        ar[i][j] = sr;
+        ai[i][j] = si;
+        ar[j][i] = sr;
+        ai[j][i] = -si;
       }
-      ar[i][j] = sr;
-      ai[i][j] = si;
-      ar[j][i] = sr;
-      ai[j][i] = -si;
-    }
-  for (int i = 0; i < K; ++i) {
-    ai[i][i] = 0.0;
-    for (int j = 0; j < K; ++j) {
-      vr[i][j] = (i == j) ? 1.0 : 0.0;
-      vi[i][j] = 0.0;
+    for (int i = 0; i < K; ++i) {
+      ai[i][i] = 0.0;
+      for (int j = 0; j < K; ++j) {
+        vr[i][j] = (i == j) ? 1.0 : 0.0;
+        vi[i][j] = 0.0;
+      }
     }
   }
+  __syncthreads();
   double scale = 0.0;
   for (int i = 0; i < K; ++i) scale += fabs(ar[i][i]);
   for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < K; ++i)
-      for (int j = i + 1; j < K; ++j) off += ar[i][j] * ar[i][j] + ai[i][j] * ai[i][j];
-    if (off <= 1e-30 * scale * scale) break;
+    if (m == 0) {
+      double off = 0.0;
+      for (int i = 0; i < K; ++i)
+        for (int j = i + 1; j < K; ++j) off += ar[i][j] * ar[i][j] + ai[i][j] * ai[i][j];
+      stop = off <= 1e-30 * scale * scale;
+    }
+    __syncthreads();
+    const int done = stop;
+    __syncthreads();  // every lane has read the flag before lane 0 can rewrite it
+    if (done) break;
     for (int pp = 0; pp < K; ++pp)
       for (int qq = pp + 1; qq < K; ++qq) {
         const double gr = ar[pp][qq], gi = ai[pp][qq];
         const double mag = sqrt(gr * gr + gi * gi);
-        if (mag == 0.0) continue;
+        if (mag == 0.0) continue;  // uniform: every lane read the same value
         // A_pq = mag e^{i th}; rotate with a real Jacobi angle on the phase-removed pair
         const double er = gr / mag, ei = gi / mag;  // e^{i th}
         const double app = ar[pp][pp], aqq = ar[qq][qq];
         const double tau = (aqq - app) / (2.0 * mag);
         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
         const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        __syncthreads();  // every lane has read the pivot before it changes
         // unitary J: columns p,q of the identity replaced by
         //   J_pp = c, J_pq = s e^{i th}, J_qp = -s e^{-i th}, J_qq = c ; A <- J^H A J
-        for (int m = 0; m < K; ++m) {  // A <- A J (columns p, q)
+        if (m < K) {  // A <- A J (columns p, q), V <- V J
           const double xr = ar[m][pp], xi = ai[m][pp], yr = ar[m][qq], yi = ai[m][qq];
           // new col p = c x - s e^{-i th} y ; new col q = s e^{i th} x + c y
           ar[m][pp] = c * xr - s * (er * yr + ei * yi);
@@ -1059,7 +1074,8 @@ __global__ void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict_
           vr[m][qq] = s * (er * ur - ei * ui) + c * wr;
           vi[m][qq] = s * (er * ui + ei * ur) + c * wi;
         }
-        for (int m = 0; m < K; ++m) {  // A <- J^H A (rows p, q)
+        __syncthreads();
+        if (m < K) {  // A <- J^H A (rows p, q)
           const double xr = ar[pp][m], xi = ai[pp][m], yr = ar[qq][m], yi = ai[qq][m];
           // new row p = c x - s e^{i th} y ; new row q = s e^{-i th} x + c y
           ar[pp][m] = c * xr - s * (er * yr - ei * yi);
@@ -1067,10 +1083,15 @@ __global__ void k_eig(const CaseDesc* __restrict__ cases, const int* __restrict_
           ar[qq][m] = s * (er * xr + ei * xi) + c * yr;
           ai[qq][m] = s * (er * xi - ei * xr) + c * yi;
         }
-        ar[pp][qq] = ai[pp][qq] = ar[qq][pp] = ai[qq][pp] = 0.0;
-        ai[pp][pp] = ai[qq][qq] = 0.0;
+        __syncthreads();
+        if (m == 0) {
+          ar[pp][qq] = ai[pp][qq] = ar[qq][pp] = ai[qq][pp] = 0.0;
+          ai[pp][pp] = ai[qq][qq] = 0.0;
+        }
+        __syncthreads();
       }
   }
+  if (m != 0) return;
   // sort by eigenvalue, descending (stable selection)
   int ord[kMaxModes];
   bool used[kMaxModes];
