@@ -101,3 +101,53 @@ def test_null_context_calls_fail_cleanly():
     lib.ptycho_destroy(None)
     assert P.ptycho_last_error(None)
     assert lib.ptycho_kernel_name(999) is None
+
+
+def test_variant_api_host_side():
+    import paper_2406_06640_amd as P
+    assert P.ptycho_variant_count() == 12
+    assert P.load_library().ptycho_set_variant(None, 1) == P.PTYCHO_E_INVALID
+
+
+def test_warm_start_abi_rejects_bad_arguments_without_device_work():
+    """Argument checks of the warm-start entry points run before any HIP call."""
+    import ctypes
+    import paper_2406_06640_amd as P
+    from paper_2406_06640_amd import learned as L
+    lib = L.ws_library()
+    assert lib.ptycho_ws_param_count() == L.PTYCHO_WS_N_PARAMS == 46692
+    h = ctypes.c_void_p()
+    assert lib.ptycho_ws_create(0, None, ctypes.byref(h)) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_create(5000, None, ctypes.byref(h)) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_create(4, None, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_forward(None, None, None, 1, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_set_params(None, None, 0) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_features(None, 1, 64, None, None) == P.PTYCHO_E_INVALID
+    dummy = ctypes.c_void_p(1)  # never dereferenced: the shape checks fail first
+    assert lib.ptycho_ws_features(dummy, 1, 130, dummy, None) == P.PTYCHO_E_SHAPE
+    assert lib.ptycho_ws_features(dummy, 1, 63, dummy, None) == P.PTYCHO_E_SHAPE
+    assert lib.ptycho_ws_features(dummy, 0, 64, dummy, None) == P.PTYCHO_E_SHAPE
+    assert lib.ptycho_ws_render_probe(64, 5, 10.0, 1.0, 1.0, dummy, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_render_probe(64, 2, 40.0, 1.0, 1.0, dummy, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_render_probe(64, 2, 10.0, 1.0, 0.0, dummy, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_ws_render_probe(4, 1, 1.0, 1.0, 1.0, dummy, None) == P.PTYCHO_E_SHAPE
+    assert L.ws_library().ptycho_ws_last_error()
+    lib.ptycho_ws_destroy(None)
+    lib.ptycho_fm_destroy(None)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("obj_side", 200, -2), ("obj_side", 100, -2), ("n_scan", 40, -2), ("n_wl", 0, -1), ("counts", 0.0, -1),
+    ("sigma_lo", -1.0, -1), ("r_hi", 40.0, -1), ("bw_hi", 0.6, -1), ("c_hi", 0.1, -1),
+])
+def test_forward_model_config_validation(field, value, status):
+    import ctypes
+    from paper_2406_06640_amd import learned as L
+    lib = L.ws_library()
+    cfg = L.FmConfig()
+    lib.ptycho_fm_default_config(ctypes.byref(cfg))
+    assert (cfg.obj_side, cfg.n_scan, cfg.step, cfg.n_wl) == (144, 10, 8, 5)
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    assert lib.ptycho_fm_create(ctypes.byref(cfg), 4, None, ctypes.byref(h)) == status
+    assert not h.value
