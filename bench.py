@@ -63,6 +63,7 @@ def per_slot_bytes(name, n, k):
         "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, vertically blurred amplitude out
         "modulus_factor": 12 * nn,                   # blurred amplitude and measurement in, factor out
         "inv_cols": 16 * k * nn + 4 * nn,            # K frames in and out, factor in
+        "cols_fused": 16 * k * nn + 4 * nn,          # K frames in and out, measurement in
         "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
         "probe_update_constraint": 8 * k * nn,       # K probe contributions in
     }.get(name)

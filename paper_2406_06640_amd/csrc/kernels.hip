@@ -29,7 +29,7 @@ namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
     "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_update", "probe_update_constraint",
-    "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor"};
+    "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor", "cols_fused"};
 
 constexpr int kThreads = 256;
 
@@ -577,6 +577,140 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restric
     return [=](int s, int c, int y, float2 v) { fr[y * N + c] = cscale(v, scale); };
   };
   mode_loop<N, C, true, true, NEAR, true>(MP ? 1 : K, buf, tw, hn, gather, store_for);
+}
+
+// The three middle passes in one workgroup per (slot, column tile): the forward
+// column transform of C + 2 kFusedHalo columns (the tile and a halo on each side,
+// wrapping at the frame edge) for every mode, the mode sum and the vertical
+// half of the blur in LDS, the horizontal half and the modulus factor for the
+// tile's C columns (the halo supplies the horizontal neighbours), then
+// Psi' = factor Psi and the inverse column transform of the tile.  The forward
+// results of the tile's columns go through X (re-read by the same workgroup),
+// so no separate blurred-amplitude or factor arrays exist.  Valid while the
+// kernel half-width is at most kFusedHalo.  Same arithmetic, element by
+// element, as fwd_cols + modulus_factor + inv_cols; the data-error partials
+// are per column tile.
+template <int N, bool NEAR, int C>
+__global__ __launch_bounds__(kThreads) void k_cols_fused(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
+  constexpr int H = kFusedHalo;
+  constexpr int NL = C + 2 * H;
+  constexpr int SS = RegShape<N, NL>::STORE_SLOTS;
+  constexpr int LS = RegShape<N, C>::LOAD_SLOTS;
+  constexpr int GX = N / C;
+  constexpr int TS = NL + 1;  // float tile row pitch
+  extern __shared__ float2 sm[];
+  __shared__ double red[kThreads / 64];
+  __shared__ float sgx[kMaxHalf + 1], sgy[kMaxHalf + 1];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  if (b >= bt.ns) return;
+  const DevParams& p = bt.cs->p;
+  const DevBufsG d = global_bufs(bt.cs->d);
+  const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* buf = sm + 2 * N;
+  const int x0 = bx * C;
+  const int pat = bt.slots[b];
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  if (threadIdx.x <= kMaxHalf) {
+    sgx[threadIdx.x] = p.gx[threadIdx.x];
+    sgy[threadIdx.x] = p.gy[threadIdx.x];
+  }
+  const int K = p.k;
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  float2* f0 = d.X + (size_t)b * K * N * N;
+  // forward: all NL columns, the tile's columns written to X, |Psi|^2 summed over modes
+  float acc[SS];
+#pragma unroll
+  for (int i = 0; i < SS; ++i) acc[i] = 0.f;
+  auto gather = [&](int k, float2* v) {
+    const float2* fr = f0 + (size_t)k * N * N;
+    auto load = [&](int s, int l, int y) { return fr[y * N + wrap(x0 - H + l, N)]; };
+    fft_gather<N, NL, true>(v, load);
+  };
+  auto store_for = [&](int k) {
+    float2* fr = f0 + (size_t)k * N * N + x0 - H;
+    return [&, fr](int s, int l, int y, float2 v) {
+      v = cscale(v, scale);
+      if (l >= H && l < H + C) fr[y * N + l] = v;
+      acc[s] += v.x * v.x + v.y * v.y;
+    };
+  };
+  mode_loop<N, NL, true, false, NEAR, false>(K, buf, tw, hn, gather, store_for);
+  // mode sum -> tile A; vertical blur -> tile B (both in the transform buffer)
+  float* ta = reinterpret_cast<float*>(buf);
+  float* tb = ta + N * TS;
+  const bool inten = p.blur_intensity != 0;
+  for_store_slots<N, NL, true>([&](int s, int l, int y) { ta[y * TS + l] = inten ? acc[s] : sqrtf(acc[s]); });
+  __syncthreads();
+  const int h = p.ks_half;
+  {
+    float gv[SS];
+    for_store_slots<N, NL, true>([&](int s, int l, int y) { gv[s] = sgy[0] * ta[y * TS + l]; });
+    for (int dy = 1; dy <= h; ++dy) {
+      const float gd = sgy[dy];
+      for_store_slots<N, NL, true>([&](int s, int l, int y) {
+        gv[s] += gd * (ta[wrap(y - dy, N) * TS + l] + ta[wrap(y + dy, N) * TS + l]);
+      });
+    }
+    for_store_slots<N, NL, true>([&](int s, int l, int y) { tb[y * TS + l] = gv[s]; });
+  }
+  __syncthreads();
+  // horizontal blur and the modulus factor for the tile's columns, in the inverse pass's slots
+  const float* amp = d.amp + (size_t)pat * N * N + x0;
+  float* dbgf = dbg.factor ? dbg.factor + (size_t)b * N * N + x0 : nullptr;
+  const float eps = p.eps;
+  float f[LS];
+  double err = 0.0;
+  {
+    float av[LS], g[LS];
+    for_load_slots<N, C, true>([&](int s, int c, int y) {
+      av[s] = amp[y * N + c];
+      g[s] = sgx[0] * tb[y * TS + H + c];
+    });
+    for (int dx = 1; dx <= h; ++dx) {
+      const float gd = sgx[dx];
+      for_load_slots<N, C, true>([&](int s, int c, int y) {
+        g[s] += gd * (tb[y * TS + H + c - dx] + tb[y * TS + H + c + dx]);
+      });
+    }
+    for_load_slots<N, C, true>([&](int s, int c, int y) {
+      const float a = av[s];
+      float ag;
+      if (inten) {
+        ag = sqrtf(g[s]);
+        f[s] = a / sqrtf(g[s] + eps * eps);
+      } else {
+        ag = g[s];
+        f[s] = a / (g[s] + eps);
+      }
+      if (dbgf) dbgf[y * N + c] = f[s];
+      const double dd = (double)a - (double)ag;
+      err += dd * dd;
+    });
+  }
+  const double tot = block_sum_d(err, red);  // also: every tile read is done before the transforms reuse buf
+  if (threadIdx.x == 0) d.err_part[(size_t)pat * GX + bx] = tot;
+  // inverse: the tile's columns
+  float2* c0 = f0 + x0;
+  auto igather = [&](int k, float2* v) {
+    const float2* fr = c0 + (size_t)k * N * N;
+    auto load = [&](int s, int c, int y) {
+      const float2 x = fr[y * N + c];
+      return make_float2(x.x * f[s], x.y * f[s]);
+    };
+    fft_gather<N, C, true>(v, load);
+  };
+  auto istore_for = [&](int k) {
+    float2* fr = c0 + (size_t)k * N * N;
+    return [=](int s, int c, int y, float2 v) { fr[y * N + c] = cscale(v, scale); };
+  };
+  mode_loop<N, C, true, true, NEAR, true>(K, buf, tw, hn, igather, istore_for);
 }
 
 // ---------------------------------------------------------------------------
@@ -1236,11 +1370,15 @@ struct TunedCols {
   static constexpr bool value = N == 64 || N == 128 || N == 192 || N == 256 || N == 512;
 };
 
-// Launch variant v: column width index v % 3 (COLS/2, COLS, 2 COLS), inverse
-// column pass mode-parallel if (v / 3) & 1, first row pass mode-parallel if (v / 6) & 1.
+// Launch variant v: column width index v % 3 (COLS/2, COLS, 2 COLS).  v < 12:
+// the three middle passes as separate launches, the inverse column pass
+// mode-parallel if (v / 3) & 1, the first row pass mode-parallel if (v / 6) & 1.
+// v in [12, 18): the fused column pass, the first row pass mode-parallel if
+// ((v - 12) / 3) & 1.
 __host__ __device__ constexpr int var_width(int v) { return v % 3; }
-__host__ __device__ constexpr bool var_mp_cols(int v) { return ((v / 3) & 1) != 0; }
-__host__ __device__ constexpr bool var_mp_rows(int v) { return ((v / 6) & 1) != 0; }
+__host__ __device__ constexpr bool var_fused(int v) { return v >= 12; }
+__host__ __device__ constexpr bool var_mp_cols(int v) { return v < 12 && ((v / 3) & 1) != 0; }
+__host__ __device__ constexpr bool var_mp_rows(int v) { return v < 12 ? ((v / 6) & 1) != 0 : (((v - 12) / 3) & 1) != 0; }
 
 template <int N>
 static int col_width_t(int v) {
@@ -1280,7 +1418,11 @@ bool col_variant_valid(int n, int v) {
       return false;
   }
 }
-int n_err_slots(int n) {
+bool fused_active(int n, int v, int max_half) {
+  return col_variant_valid(n, v) && var_fused(v) && max_half <= kFusedHalo;
+}
+int n_err_slots(int n, int v, int max_half) {
+  if (fused_active(n, v, max_half)) return n / col_width(n, v);
   switch (n) {
 #define PTY_CASE(N) \
   case N:           \
@@ -1290,6 +1432,12 @@ int n_err_slots(int n) {
     default:
       return 1;
   }
+}
+int max_err_slots(int n) {
+  int m = 0;
+  for (int v = 0; v < kColVariants; ++v)
+    if (col_variant_valid(n, v)) m = std::max(m, n_err_slots(n, v, 0));
+  return m;
 }
 int n_obj_tiles(const DevParams& p) { return tiles_of(p); }
 int n_probe_blocks(int n) { return n_probe_blocks_dev(n); }
@@ -1330,6 +1478,24 @@ static hipError_t fwd_cols_v(const CaseDesc* cases, const TableShape& t, int bet
   hipLaunchKernelGGL((k_fwd_cols<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
                      cases, beta, it);
   return hipGetLastError();
+}
+template <int N, bool NEAR, int V>
+static hipError_t cols_fused_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  constexpr int C = ColW<N, V>::C;
+  constexpr int NL = C + 2 * kFusedHalo;
+  const size_t sh = sizeof(float2) * (2 * N + Frame<N, NL, true>::ELEMS);
+  hipLaunchKernelGGL((k_cols_fused<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s, cases,
+                     beta, it);
+  return hipGetLastError();
+}
+template <int N, bool NEAR>
+static hipError_t cols_fused_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  if constexpr (TunedCols<N>::value) {
+    if (var_width(t.col_variant) == 0) return cols_fused_v<N, NEAR, 0>(cases, t, beta, it, s);
+    if (var_width(t.col_variant) == 2) return cols_fused_v<N, NEAR, 2>(cases, t, beta, it, s);
+    return cols_fused_v<N, NEAR, 1>(cases, t, beta, it, s);
+  }
+  return hipErrorInvalidValue;
 }
 template <int N>
 static hipError_t factor_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
@@ -1393,6 +1559,10 @@ static hipError_t inv_cols_t(const CaseDesc* cases, const TableShape& t, int bet
   case N:                  \
     return factor_t<N>(cases, t, beta, it, s);
 PTY_DEFINE_LAUNCH(factor)
+#define PTY_CASE_cols_fused(N) \
+  case N:                      \
+    return t.near_field ? cols_fused_t<N, true>(cases, t, beta, it, s) : cols_fused_t<N, false>(cases, t, beta, it, s);
+PTY_DEFINE_LAUNCH(cols_fused)
 PTY_DEFINE_LAUNCH(fwd_rows)
 PTY_DEFINE_LAUNCH(inv_rows)
 PTY_DEFINE_LAUNCH(fwd_cols)

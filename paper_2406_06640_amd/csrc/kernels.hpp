@@ -20,9 +20,12 @@ constexpr int kMaxModes = 16;
 constexpr int kMaxBatch = 256;
 constexpr int kObjTile = 32;     // object tile side for the gather/update kernels
 constexpr int kGramBlocks = 16;  // pixel chunks of the Gram matrix reduction
-// launch variants tried by the autotuner: column-tile width COLS/2, COLS or 2 COLS (v % 3),
-// mode-parallel inverse column pass ((v / 3) & 1), mode-parallel first row pass ((v / 6) & 1)
-constexpr int kColVariants = 12;
+// launch variants tried by the autotuner: column-tile width COLS/2, COLS or 2 COLS (v % 3);
+// v < 12: separate middle passes, mode-parallel inverse column pass ((v / 3) & 1), mode-parallel
+// first row pass ((v / 6) & 1); v in [12, 18): fused middle pass, mode-parallel first row pass
+// (((v - 12) / 3) & 1)
+constexpr int kColVariants = 18;
+constexpr int kFusedHalo = 5;  // halo columns of the fused middle pass (kernel sizes up to 11)
 
 // Per-iteration flags of a case.
 enum : int { FLAG_PROBE = 1, FLAG_CC = 2, FLAG_ORTHO = 4 };
@@ -89,12 +92,13 @@ struct TableShape {
   int max_k;           // max over cases of the number of modes
   int max_side_jobs;   // max over cases of object tiles + V blocks
   int col_variant;     // 0..kColVariants-1
+  int max_half;        // max over cases of the blur half-width
 };
 
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_POST, KC_GRAM, KC_EIG, KC_REMIX,
-  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COUNT
+  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -104,6 +108,7 @@ extern const char* const kKernelNames[KC_COUNT];
 hipError_t launch_fwd_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_fwd_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_factor(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_cols_fused(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
@@ -135,7 +140,11 @@ hipError_t launch_dft_blur_apply(const CaseDesc* cases, const TableShape& t, int
 hipError_t launch_dft_delta(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 
 int n_obj_tiles(const DevParams& p);
-int n_err_slots(int n);  // data-error partials per position (one per row block of the factor pass)
+// data-error partials per position for launch variant v: one per column tile of the fused
+// middle pass when it runs (fused_active), else one per row block of the factor pass
+bool fused_active(int n, int v, int max_half);
+int n_err_slots(int n, int v, int max_half);
+int max_err_slots(int n);  // over every variant
 int n_probe_blocks(int n);
 int col_width(int n, int col_variant);    // columns per column block
 bool col_variant_valid(int n, int col_variant);

@@ -300,9 +300,13 @@ void harvest_timing(ptycho_ctx* c) {
 std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
                          hipStream_t s) {
   LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_FWD_COLS, s, launch_fwd_cols(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_FACTOR, s, launch_factor(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_INV_COLS, s, launch_inv_cols(cases, sh, beta, it, s));
+  if (fused_active(sh.n, sh.col_variant, sh.max_half)) {
+    LAUNCH(tc, KC_COLS_FUSED, s, launch_cols_fused(cases, sh, beta, it, s));
+  } else {
+    LAUNCH(tc, KC_FWD_COLS, s, launch_fwd_cols(cases, sh, beta, it, s));
+    LAUNCH(tc, KC_FACTOR, s, launch_factor(cases, sh, beta, it, s));
+    LAUNCH(tc, KC_INV_COLS, s, launch_inv_cols(cases, sh, beta, it, s));
+  }
   LAUNCH(tc, KC_INV_ROWS, s, launch_inv_rows(cases, sh, beta, it, s));
   LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
   LAUNCH(tc, KC_POST, s, launch_post(cases, sh, beta, it, s));
@@ -357,7 +361,7 @@ void fill_case(const ptycho_ctx* c, CaseDesc& cd, const int* order, const int* f
   cd.n_pos = c->prm.n_pos;
   cd.batch = c->prm.batch;
   cd.n_batches = n_batches_of(c->prm);
-  cd.n_err_part = c->prm.n_pos * (c->prm.dft_bf16 ? dft_err_slots(c->prm.n) : n_err_slots(c->prm.n));
+  cd.n_err_part = c->prm.n_pos * (c->prm.dft_bf16 ? dft_err_slots(c->prm.n) : n_err_slots(c->prm.n, c->col_variant, c->dp.ks_half));
 }
 
 TableShape single_shape(const ptycho_ctx* c, int max_batch) {
@@ -370,6 +374,7 @@ TableShape single_shape(const ptycho_ctx* c, int max_batch) {
   sh.max_k = c->prm.n_modes;
   sh.max_side_jobs = sh.max_tiles + n_probe_blocks(c->prm.n);
   sh.col_variant = c->col_variant;
+  sh.max_half = c->dp.ks_half;
   return sh;
 }
 
@@ -658,7 +663,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   double *errp, *eig;
   double2 *ccp, *gramp;
   const int nobjt = n_obj_tiles(dp);
-  const int nbt = std::max(n_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
+  const int nbt = std::max(max_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
   ptycho_status st = PTYCHO_OK;
   if ((st = dev_alloc(c, &obj, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &probe, K * nn)) ||
       (st = dev_alloc(c, &pw, nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
@@ -1163,6 +1168,7 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
     sh.max_tiles = std::max(sh.max_tiles, n_obj_tiles(c->dp));
     sh.max_k = std::max(sh.max_k, c->prm.n_modes);
     sh.max_side_jobs = std::max(sh.max_side_jobs, n_obj_tiles(c->dp) + n_probe_blocks(c->prm.n));
+    sh.max_half = std::max(sh.max_half, c->dp.ks_half);
   }
   for (auto& tb : g->tables) {
     void* p = nullptr;
@@ -1280,7 +1286,7 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
       const int i = tb.members[m];
       fill_case(g->ctx[i], tb.h_cases[m], g->call.d_order + off[i], g->call.d_flags + (size_t)i * n_iter,
                 g->call.d_err + (size_t)i * n_iter);
-      tb.h_cases[m].n_err_part = g->ctx[i]->prm.n_pos * n_err_slots(tb.shape.n);
+      tb.h_cases[m].n_err_part = g->ctx[i]->prm.n_pos * n_err_slots(tb.shape.n, tb.shape.col_variant, tb.shape.max_half);
     }
   HIP_GTRY(g, hipMemcpyAsync(g->call.d_order, g->call.h_order, off[nc] * sizeof(int), hipMemcpyHostToDevice, s));
   HIP_GTRY(g, hipMemcpyAsync(g->call.d_flags, g->call.h_flags, (size_t)n_iter * nc * sizeof(int),
