@@ -60,12 +60,12 @@ def per_slot_bytes(name, n, k):
     nn = n * n
     return {
         "fwd_rows": 16 * nn + 8 * k * nn,            # box gather in (exit waves and V), K frames out
-        "fwd_cols": 16 * k * nn + 4 * nn,            # K frames in and out, vertically blurred amplitude out
+        "fwd_cols": 8 * k * nn + 4 * nn,             # K frames in (far field: not written back), blurred amplitude out
         "modulus_factor": 12 * nn,                   # blurred amplitude and measurement in, factor out
-        "inv_cols": 16 * k * nn + 4 * nn,            # K frames in and out, factor in
+        "inv_cols": 16 * k * nn + 4 * nn,            # K row-transformed frames in, K frames out, factor in
         "cols_fused": 16 * k * nn + 4 * nn,          # K frames in and out, measurement in
         "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
-        "probe_update_constraint": 8 * k * nn,       # K probe contributions in
+        "obj_probe_update": 8 * k * nn + 12 * nn,   # K probe contributions in; object numerator and W gather in
     }.get(name)
 
 

@@ -190,7 +190,8 @@ __global__ __launch_bounds__(kThreads) void k_dft_side(const CaseDesc* __restric
   __shared__ SideScratch sc;
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
-  side_job(bt.cs->p, global_bufs(bt.cs->d), bt.slots, bt.ns, blockIdx.x, (bt.flags & FLAG_PROBE) != 0, sc);
+  side_job(bt.cs->p, global_bufs(bt.cs->d), pw_copy(bt.flags, beta), bt.slots, bt.ns, blockIdx.x,
+           (bt.flags & FLAG_PROBE) != 0, sc);
 }
 
 // q[b] = sum_k |Psi_k|^2 (intensity blur) or its square root (amplitude blur).

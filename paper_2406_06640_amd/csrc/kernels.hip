@@ -28,7 +28,7 @@
 namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
-    "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_update", "probe_update_constraint",
+    "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_probe_update", "complex_constraint",
     "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor", "cols_fused"};
 
 constexpr int kThreads = 256;
@@ -66,6 +66,19 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh) {
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Two sums at once, each in the order of block_sum_d (same results, half the barriers).
+__device__ __forceinline__ double2 block_sum_d2(double a, double b, double2* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = make_double2(a, b);
+  __syncthreads();
+  return make_double2((sh[0].x + sh[1].x) + (sh[2].x + sh[3].x), (sh[0].y + sh[1].y) + (sh[2].y + sh[3].y));
 }
 
 __device__ __forceinline__ float block_max_f(float v, float* sh) {
@@ -167,6 +180,13 @@ __device__ __forceinline__ bool open_batch(const CaseDesc* cases, int beta, cons
   return true;
 }
 
+// Copy of the probe-power map that batch `beta` reads: FLAG_PW_ODD gives the
+// copy of the iteration's first batch; batches that update the probe alternate
+// (each writes the copy the next one reads); without probe update all read one.
+__device__ __forceinline__ int pw_copy(int flags, int beta) {
+  return ((flags & FLAG_PW_ODD) ? 1 : 0) ^ ((flags & FLAG_PROBE) ? (beta & 1) : 0);
+}
+
 template <class T, class = void>
 struct HasPre : std::false_type {};
 template <class T>
@@ -211,9 +231,36 @@ __device__ __forceinline__ void mode_loop(int K, float2* buf, const float2* tw, 
   }
 }
 
+// Far-field inverse column pass that recomputes its input: per mode, the
+// forward transform of the row-transformed frame (what the forward column pass
+// computed, scaled by `fscale`) goes to LDS instead of global memory, and the
+// inverse transform gathers it from there through `scale_in(slot, x)` (the
+// modulus factor).  Same operations, in the same order, as storing the forward
+// result to global memory and reading it back.
+template <int N, int NL, class Gather, class ScaleIn, class StoreFor>
+__device__ __forceinline__ void mode_loop_refwd(int K, float2* buf, const float2* tw, float fscale, Gather& gather,
+                                                ScaleIn& scale_in, StoreFor& store_for) {
+  using F = Frame<N, NL, true>;
+  constexpr bool SINGLE = RegShape<N, NL>::SINGLE;
+  float2 v[RegShape<N, NL>::LOAD_SLOTS];
+  auto to_lds = [&](int s, int line, int pos, float2 x) { buf[F::lidx(line, pos)] = cscale(x, fscale); };
+  auto from_lds = [&](int s, int line, int pos) { return scale_in(s, buf[F::lidx(line, pos)]); };
+  gather(0, v);
+  for (int k = 0; k < K; ++k) {
+    auto store = store_for(k);
+    fft_first<N, NL, true, false>(v, buf);
+    if (!SINGLE && k + 1 < K) gather(k + 1, v);
+    fft_rest<N, NL, true, false, true>(v, buf, tw, to_lds);
+    if (SINGLE && k + 1 < K) gather(k + 1, v);
+    __syncthreads();
+    fft_reg<N, NL, true, true, true, false>(buf, tw, from_lds, store);
+    __syncthreads();
+  }
+}
+
 struct SideScratch;
-__device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots, int ns, int job, bool with_v,
-                         SideScratch& sc);
+__device__ void side_job(const DevParams& p, const DevBufsG& d, int pwc, const int* slots, int ns, int job,
+                         bool with_v, SideScratch& sc);
 
 // Mode-parallel launches (MP) give every (slot, line block, mode) its own
 // workgroup.  Workgroups are dispatched to the 8 XCDs round-robin, so the modes
@@ -243,8 +290,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restric
   int b, bx, k0 = 0;
   if (MP) {
     if ((int)blockIdx.x >= main_blocks) {
-      side_job(p, d, bt.slots, bt.ns, (int)blockIdx.x - main_blocks, (bt.flags & FLAG_PROBE) != 0,
-               *reinterpret_cast<SideScratch*>(sm));
+      side_job(p, d, pw_copy(bt.flags, beta), bt.slots, bt.ns,
+               (int)blockIdx.x - main_blocks, (bt.flags & FLAG_PROBE) != 0, *reinterpret_cast<SideScratch*>(sm));
       return;
     }
     int tile;
@@ -256,8 +303,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows(const CaseDesc* __restric
     b = blockIdx.x / GX;
     bx = blockIdx.x % GX;
     if (b >= bt.ns) {
-      side_job(p, d, bt.slots, bt.ns, (b - bt.ns) * GX + bx, (bt.flags & FLAG_PROBE) != 0,
-               *reinterpret_cast<SideScratch*>(sm));
+      side_job(p, d, pw_copy(bt.flags, beta), bt.slots, bt.ns, (b - bt.ns) * GX + bx,
+               (bt.flags & FLAG_PROBE) != 0, *reinterpret_cast<SideScratch*>(sm));
       return;
     }
   }
@@ -377,7 +424,9 @@ __device__ __forceinline__ int wrap(int t, int n) {
 
 // Forward column transform of every mode, the incoherent mode sum, and the
 // vertical (sigma2) half of the separable Gaussian blur of Eq. (6) (or of the
-// intensity, Eq. 2): q = g_y (x) sqrt(sum_k |Psi_k|^2).
+// intensity, Eq. 2): q = g_y (x) sqrt(sum_k |Psi_k|^2).  Only q leaves the
+// workgroup in the far field (the inverse column pass recomputes Psi_k, which
+// costs less than a write and a read of K frames); near-field Psi_k are stored.
 template <int N, bool NEAR, int C>
 __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   constexpr int SS = RegShape<N, C>::STORE_SLOTS;
@@ -411,11 +460,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
     auto load = [&](int s, int c, int y) { return fr[y * N + c]; };
     fft_gather<N, C, true>(v, load);
   };
+  // the far-field inverse column pass recomputes this transform, so only the
+  // near-field frames are written back
   auto store_for = [&](int k) {
     float2* fr = f0 + (size_t)k * N * N;
     return [&, fr](int s, int c, int y, float2 v) {
       v = cscale(v, scale);
-      fr[y * N + c] = v;
+      if (NEAR) fr[y * N + c] = v;
       acc[s] += v.x * v.x + v.y * v.y;
     };
   };
@@ -523,8 +574,9 @@ __global__ __launch_bounds__(kThreads) void k_factor(const CaseDesc* __restrict_
   if (threadIdx.x == 0) d.err_part[(size_t)pat * GX + by] = tot;
 }
 
-// Psi' = factor Psi and the inverse column transform.  MP launches take one
-// mode per workgroup (see mp_decode).
+// Psi' = factor Psi and the inverse column transform, Psi_k recomputed from the
+// row-transformed frame in the far field (mode_loop_refwd) and read back in the
+// near field.  MP launches take one mode per workgroup (see mp_decode).
 template <int N, bool NEAR, int C, bool MP>
 __global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it,
                                                        int km) {
@@ -561,22 +613,33 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restric
   const int K = p.k;
   const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
   float2* f0 = d.X + ((size_t)b * K + k0) * N * N + x0;
-  auto gather = [&](int k, float2* v) {
-    const float2* fr = f0 + (size_t)k * N * N;
-    auto load = [&](int s, int c, int y) {
-      // a rounded product of its own, never fused into the first butterflies:
-      // serial and mode-parallel launches then give bitwise the same frames
+  // Psi' = f Psi: a rounded product of its own, never fused into the first
+  // butterflies, so serial and mode-parallel launches give bitwise the same frames
+  auto times_f = [&](int s, float2 x) {
 #pragma clang fp contract(off)
-      const float2 x = fr[y * N + c];
-      return make_float2(x.x * f[s], x.y * f[s]);
-    };
-    fft_gather<N, C, true>(v, load);
+    return make_float2(x.x * f[s], x.y * f[s]);
   };
   auto store_for = [&](int k) {
     float2* fr = f0 + (size_t)k * N * N;
     return [=](int s, int c, int y, float2 v) { fr[y * N + c] = cscale(v, scale); };
   };
-  mode_loop<N, C, true, true, NEAR, true>(MP ? 1 : K, buf, tw, hn, gather, store_for);
+  if constexpr (NEAR) {
+    // near field: Psi_k as the forward column pass stored it
+    auto gather = [&](int k, float2* v) {
+      const float2* fr = f0 + (size_t)k * N * N;
+      auto load = [&](int s, int c, int y) { return times_f(s, fr[y * N + c]); };
+      fft_gather<N, C, true>(v, load);
+    };
+    mode_loop<N, C, true, true, NEAR, true>(MP ? 1 : K, buf, tw, hn, gather, store_for);
+  } else {
+    // far field: Psi_k recomputed from the row-transformed frame
+    auto gather = [&](int k, float2* v) {
+      const float2* fr = f0 + (size_t)k * N * N;
+      auto load = [&](int s, int c, int y) { return fr[y * N + c]; };
+      fft_gather<N, C, true>(v, load);
+    };
+    mode_loop_refwd<N, C>(MP ? 1 : K, buf, tw, scale, gather, times_f, store_for);
+  }
 }
 
 // The three middle passes in one workgroup per (slot, column tile): the forward
@@ -751,12 +814,6 @@ __device__ __forceinline__ int tile_list(const DevBufsG& d, const int* slots, in
   return total;
 }
 
-__device__ __forceinline__ float reduce_max_parts(const float* parts, int count, float* red) {
-  float m = 0.f;
-  for (int i = threadIdx.x; i < count; i += kThreads) m = fmaxf(m, parts[i]);
-  return block_max_f(m, red);
-}
-
 __host__ __device__ __forceinline__ int tiles_x_of(const DevParams& p) { return (p.w_obj + kObjTile - 1) / kObjTile; }
 __host__ __device__ __forceinline__ int tiles_of(const DevParams& p) {
   return tiles_x_of(p) * ((p.h_obj + kObjTile - 1) / kObjTile);
@@ -776,8 +833,8 @@ struct SideScratch {
 // before any update of the batch): job < tiles: the maximum over one object
 // tile of W(r) = sum_b sum_k |P_k(r - r_b)|^2; next jobs (probe update only):
 // V(pix) = sum_b |o_b(pix)|^2 over one block of probe pixels and its maximum.
-__device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots, int ns, int job, bool with_v,
-                         SideScratch& sc) {
+__device__ void side_job(const DevParams& p, const DevBufsG& d, int pwc, const int* slots, int ns, int job,
+                         bool with_v, SideScratch& sc) {
   const int n = p.n;
   const int tiles_x = tiles_x_of(p);
   const int tiles = tiles_of(p);
@@ -792,7 +849,7 @@ __device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots
     float w[kTilePix];
 #pragma unroll
     for (int q = 0; q < kTilePix; ++q) w[q] = 0.f;
-    const float* pw = d.pw;
+    const float* pw = d.pw + (size_t)pwc * n * n;
     for (int i0 = 0; i0 < cnt; i0 += 4) {  // four slots' loads in flight, summed in slot order
       float wv[4][kTilePix];
 #pragma unroll
@@ -858,20 +915,122 @@ __device__ void side_job(const DevParams& p, const DevBufsG& d, const int* slots
   if (threadIdx.x == 0) d.maxv_part[vb] = m;
 }
 
-// Object update (gathered per tile, slots in ascending order).  Inside a
-// constraint window it also writes this tile's share of the C-bar sums of
-// Eq. (11): each pixel counted once per box that covers it.
+__host__ __device__ __forceinline__ int pow2_at_least(int k) {
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  return kp;
+}
+// Probe blocks: KP threads per pixel pair (KP = K rounded up to a power of 2);
+// a thread takes two adjacent pixels of one mode (one 16-byte load per slot) and
+// keeps four partial sums over the slots (slot b goes to sum b mod 4).
+constexpr int kPostPx = 2;
+constexpr int kPostUnroll = 4;
+__host__ __device__ __forceinline__ int post_probe_blocks(int n, int k) {
+  const int px_per = kThreads / pow2_at_least(k);
+  const int groups = (n * n + kPostPx - 1) / kPostPx;
+  return (groups + px_per - 1) / px_per;
+}
+
+// Probe update of one block of probe pixels: numerator N_P,k = sum_b X[b][k]
+// (a fixed order: four interleaved partial sums over the slots, combined
+// pairwise), P_k += beta N_P,k / ((1-g) V + g max V), and sum_k |P_k|^2 into the
+// probe-power copy that the next batch reads.
+__device__ __forceinline__ void probe_update_block(const DevParams& p, const DevBufsG& d, const Batch& bt, int beta,
+                                                   float* pk2, float* red) {
+  const int n = p.n, K = p.k, ns = bt.ns;
+  const size_t nn = (size_t)n * n;
+  float* pw_next = d.pw + (size_t)(pw_copy(bt.flags, beta) ^ 1) * nn;
+  const int px_per = kThreads / pow2_at_least(K);
+  const int k = threadIdx.x / px_per, px = threadIdx.x % px_per;
+  const int pix = (blockIdx.x * px_per + px) * kPostPx;
+  const bool act = k < K && pix < n * n;
+  // every load is issued before the first wait: the V-maximum partials, V and
+  // P_k at the thread's pixels, then the slots of the numerator sum
+  float mv = 0.f;
+  for (int i = threadIdx.x; i < n_probe_blocks_dev(n); i += kThreads) mv = fmaxf(mv, d.maxv_part[i]);
+  float2 s[kPostUnroll][kPostPx], pv[kPostPx];
+  float vv[kPostPx];
+#pragma unroll
+  for (int j = 0; j < kPostPx; ++j) {
+    vv[j] = act ? d.V[pix + j] : 0.f;
+    pv[j] = act ? d.probe[(size_t)k * nn + pix + j] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < kPostUnroll; ++u) s[u][j] = make_float2(0.f, 0.f);
+  }
+  if (act) {
+    // n is even, so a pixel pair never straddles the frame end and is 16-byte aligned
+    const float4* x = reinterpret_cast<const float4*>(d.X + (size_t)k * nn + pix);
+    const size_t st = (size_t)K * nn / kPostPx;
+    auto add = [&](float2* acc, const float4& w) {
+      acc[0] = cadd(acc[0], make_float2(w.x, w.y));
+      acc[1] = cadd(acc[1], make_float2(w.z, w.w));
+    };
+    int b = 0;
+    for (; b + kPostUnroll <= ns; b += kPostUnroll) {
+      float4 w[kPostUnroll];
+#pragma unroll
+      for (int u = 0; u < kPostUnroll; ++u) w[u] = x[(size_t)(b + u) * st];
+#pragma unroll
+      for (int u = 0; u < kPostUnroll; ++u) add(s[u], w[u]);
+    }
+    for (; b < ns; ++b) add(s[0], x[(size_t)b * st]);
+  }
+  const float maxv = block_max_f(mv, red);
+  float mag2[kPostPx];
+#pragma unroll
+  for (int j = 0; j < kPostPx; ++j) {
+    mag2[j] = 0.f;
+    if (!act) continue;
+    // partial sums combined pairwise: (s0 + s2) + (s1 + s3)
+    const float2 np = cadd(cadd(s[0][j], s[2][j]), cadd(s[1][j], s[3][j]));
+    const size_t q = (size_t)k * nn + pix + j;
+    float2 v = pv[j];
+    d.nP[q] = np;
+    const float den = (1.0f - p.gamma_probe) * vv[j] + p.gamma_probe * maxv;
+    if (den > 0.f) {
+      const float sc = p.probe_step / den;
+      v.x += sc * np.x;
+      v.y += sc * np.y;
+      d.probe[q] = v;
+    }
+    mag2[j] = v.x * v.x + v.y * v.y;
+  }
+#pragma unroll
+  for (int j = 0; j < kPostPx; ++j) pk2[j * kThreads + threadIdx.x] = mag2[j];
+  __syncthreads();
+  if (k == 0 && pix < n * n) {
+#pragma unroll
+    for (int j = 0; j < kPostPx; ++j) {
+      float pw = 0.f;
+      for (int kk = 0; kk < K; ++kk) pw += pk2[j * kThreads + kk * px_per + px];
+      pw_next[pix + j] = pw;
+    }
+  }
+}
+
+// Object and probe update of a batch in one launch (both read only the state
+// before the batch): blocks [0, probe blocks) update the probe (probe_update_block,
+// only in iterations with probe update); the next blocks, one per object tile,
+// gather the object update over the covering slots in ascending order.  Inside a
+// constraint window a tile also writes its share of the C-bar sums of Eq. (11):
+// each pixel counted once per box that covers it.
 __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   __shared__ TileList tl;
   __shared__ float red[kThreads / 64];
-  __shared__ double redd[kThreads / 64];
+  __shared__ double2 redd[kThreads / 64];
+  __shared__ float pk2[kPostPx * kThreads];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
   const DevBufsG d = global_bufs(bt.cs->d);
   const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
+  const int pb = (bt.flags & FLAG_PROBE) ? post_probe_blocks(p.n, p.k) : 0;
+  if ((int)blockIdx.x < pb) {
+    probe_update_block(p, d, bt, beta, pk2, red);
+    return;
+  }
   const int tiles = tiles_of(p), tiles_x = tiles_x_of(p);
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x - pb;
   if (tile >= tiles) return;
   const bool cc_sums = (bt.flags & FLAG_CC) != 0;
   const int n = p.n;
@@ -881,9 +1040,19 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
     if (cc_sums && threadIdx.x == 0) d.cc_part[tile] = make_double2(0.0, 0.0);
     return;
   }
-  const float maxw = reduce_max_parts(d.maxw_part, tiles, red);
   const size_t nn = (size_t)n * n;
   const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
+  const int c = c0 + tx;
+  // loads that do not depend on the gathers are issued with them: the W-maximum
+  // partials and the tile's object values
+  float mw = 0.f;
+  for (int i = threadIdx.x; i < tiles; i += kThreads) mw = fmaxf(mw, d.maxw_part[i]);
+  float2 ov[kTilePix];
+#pragma unroll
+  for (int q = 0; q < kTilePix; ++q) {
+    const int r = r0 + ty + q * kTileRowsPerPass;
+    ov[q] = (r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
+  }
   float w[kTilePix];
   float2 num[kTilePix];
   int mult[kTilePix];
@@ -896,7 +1065,7 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
   // slots are visited in ascending order; the loads of kGather slots are issued
   // together before their (in-order) accumulation
   constexpr int kGather = 4;
-  const float* pw = d.pw;
+  const float* pw = d.pw + (size_t)pw_copy(bt.flags, beta) * nn;
   for (int i0 = 0; i0 < cnt; i0 += kGather) {
     float wv[kGather][kTilePix];
     float2 nv[kGather][kTilePix];
@@ -925,15 +1094,9 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
           ++mult[q];
         }
   }
+  const float maxw = block_max_f(mw, red);
   const float gam = p.gamma_obj, step = p.obj_step;
   float sa = 0.f, sp = 0.f;
-  const int c = c0 + tx;
-  float2 ov[kTilePix];
-#pragma unroll
-  for (int q = 0; q < kTilePix; ++q) {
-    const int r = r0 + ty + q * kTileRowsPerPass;
-    ov[q] = (mult[q] && r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
-  }
 #pragma unroll
   for (int q = 0; q < kTilePix; ++q) {
     const int r = r0 + ty + q * kTileRowsPerPass;
@@ -958,104 +1121,52 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
     }
   }
   if (cc_sums) {
-    const double ta = block_sum_d((double)sa, redd);
-    const double tp = block_sum_d((double)sp, redd);
-    if (threadIdx.x == 0) d.cc_part[tile] = make_double2(ta, tp);
+    const double2 t = block_sum_d2((double)sa, (double)sp, redd);
+    if (threadIdx.x == 0) d.cc_part[tile] = t;
   }
 }
 
-__host__ __device__ __forceinline__ int pow2_at_least(int k) {
-  int kp = 1;
-  while (kp < k) kp <<= 1;
-  return kp;
-}
-__host__ __device__ __forceinline__ int post_probe_blocks(int n, int k) {
-  const int px_per = kThreads / pow2_at_least(k);
-  return (n * n + px_per - 1) / px_per;
-}
-
-// The updates that follow the object update in one launch:
-//  blocks [0, probe blocks): probe numerator N_P,k = sum_b X[b][k] (slots in
-//    ascending order) and the probe update P_k += beta N_P,k / ((1-g) V + g max V),
-//    then sum_k |P_k|^2.  KP threads per pixel (KP = K rounded up to a power of 2).
-//  next blocks, one per object tile: the complex constraint, Eq. (9)-(10), on
-//    the tile's pixels that lie in the union of the batch boxes.
-__global__ __launch_bounds__(kThreads) void k_post(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
+// The complex constraint, Eq. (9)-(10), on one object tile per block: on the
+// tile's pixels that lie in the union of the batch boxes, with C-bar from the
+// partial sums the object update wrote.
+__global__ __launch_bounds__(kThreads) void k_constraint(const CaseDesc* __restrict__ cases, int beta,
+                                                         const int* __restrict__ it) {
   __shared__ TileList tl;
-  __shared__ float red[kThreads / 64];
-  __shared__ double redd[kThreads / 64];
-  __shared__ float pk2[kThreads];
+  __shared__ double2 redd[kThreads / 64];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
   const DevBufsG d = global_bufs(bt.cs->d);
-  const int n = p.n, K = p.k;
-  const size_t nn = (size_t)n * n;
-  const bool probe = (bt.flags & FLAG_PROBE) != 0, cc = (bt.flags & FLAG_CC) != 0;
-  const int pb = probe ? post_probe_blocks(n, K) : 0;
+  const int n = p.n;
   const int tiles = tiles_of(p);
   const int ns = bt.ns;
-  if ((int)blockIdx.x < pb) {
-    const float maxv = reduce_max_parts(d.maxv_part, n_probe_blocks_dev(n), red);
-    const int px_per = kThreads / pow2_at_least(K);
-    const int k = threadIdx.x / px_per, px = threadIdx.x % px_per;
-    const int pix = blockIdx.x * px_per + px;
-    float mag2 = 0.f;
-    if (k < K && pix < n * n) {
-      const float2* x = d.X + (size_t)k * nn + pix;
-      const size_t st = (size_t)K * nn;
-      float2 s0 = make_float2(0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
-      int b = 0;
-      for (; b + 4 <= ns; b += 4) {
-        s0 = cadd(s0, x[(size_t)b * st]);
-        s1 = cadd(s1, x[(size_t)(b + 1) * st]);
-        s2 = cadd(s2, x[(size_t)(b + 2) * st]);
-        s3 = cadd(s3, x[(size_t)(b + 3) * st]);
-      }
-      for (; b < ns; ++b) s0 = cadd(s0, x[(size_t)b * st]);
-      const float2 np = cadd(cadd(s0, s1), cadd(s2, s3));
-      const float vv = d.V[pix];
-      float2 v = d.probe[(size_t)k * nn + pix];
-      d.nP[(size_t)k * nn + pix] = np;
-      const float den = (1.0f - p.gamma_probe) * vv + p.gamma_probe * maxv;
-      if (den > 0.f) {
-        const float sc = p.probe_step / den;
-        v.x += sc * np.x;
-        v.y += sc * np.y;
-        d.probe[(size_t)k * nn + pix] = v;
-      }
-      mag2 = v.x * v.x + v.y * v.y;
-    }
-    pk2[threadIdx.x] = mag2;
-    __syncthreads();
-    if (k == 0 && pix < n * n) {
-      float pw = 0.f;
-      for (int kk = 0; kk < K; ++kk) pw += pk2[kk * px_per + px];
-      d.pw[pix] = pw;
-    }
-    return;
-  }
-  // complex constraint on one object tile
-  const int tile = blockIdx.x - pb;
-  if (!cc || tile >= tiles) return;
+  const int tile = blockIdx.x;
+  if (!(bt.flags & FLAG_CC) || tile >= tiles) return;
   const int tiles_x = tiles_x_of(p);
   const int r0 = (tile / tiles_x) * kObjTile, c0 = (tile % tiles_x) * kObjTile;
   const int cnt = tile_list(d, bt.slots, ns, n, r0, c0, tl);
   if (cnt == 0) return;
+  const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
+  const int c = c0 + tx;
+  // the tile's object values are loaded together with the C-bar partials
+  float2 ov[kTilePix];
+#pragma unroll
+  for (int q = 0; q < kTilePix; ++q) {
+    const int r = r0 + ty + q * kTileRowsPerPass;
+    ov[q] = (r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
+  }
   double sa = 0.0, sp = 0.0;
   for (int i = threadIdx.x; i < tiles; i += kThreads) {
-    sa += d.cc_part[i].x;
-    sp += d.cc_part[i].y;
+    const double2 v = d.cc_part[i];
+    sa += v.x;
+    sp += v.y;
   }
-  sa = block_sum_d(sa, redd);
-  sp = block_sum_d(sp, redd);
-  if (!(sp > 0.0)) return;
-  float cbar = (float)(sa / sp);
+  const double2 tot = block_sum_d2(sa, sp, redd);
+  if (!(tot.y > 0.0)) return;
+  float cbar = (float)(tot.x / tot.y);
   cbar = fminf(fmaxf(cbar, p.cbar_min), p.cbar_max);
   const float inv_c = 1.0f / cbar;
   const float a1 = p.alpha1, a2 = p.alpha2;
-  const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
-  const int c = c0 + tx;
 #pragma unroll
   for (int q = 0; q < kTilePix; ++q) {
     const int r = r0 + ty + q * kTileRowsPerPass;
@@ -1067,7 +1178,7 @@ __global__ __launch_bounds__(kThreads) void k_post(const CaseDesc* __restrict__ 
     }
     if (!cov) continue;
     const size_t oi = (size_t)r * p.w_obj + c;
-    const float2 o = d.obj[oi];
+    const float2 o = ov[q];
     const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
     const float phi = atan2f(o.y, o.x);
     const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
@@ -1078,7 +1189,7 @@ __global__ __launch_bounds__(kThreads) void k_post(const CaseDesc* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
+__global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d, int copy) {
   const int n = p.n;
   const size_t nn = (size_t)n * n;
   const int pix = blockIdx.x * kThreads + threadIdx.x;
@@ -1088,7 +1199,7 @@ __global__ __launch_bounds__(kThreads) void k_pw(DevParams p, DevBufs d) {
     const float2 v = d.probe[(size_t)k * nn + pix];
     pw += v.x * v.x + v.y * v.y;
   }
-  d.pw[pix] = pw;
+  d.pw[copy * nn + pix] = pw;
 }
 
 // ---------------------------------------------------------------------------
@@ -1276,7 +1387,7 @@ __global__ __launch_bounds__(kThreads) void k_remix(const CaseDesc* __restrict__
     d.probe[(size_t)j * nn + pix] = s;
     pw += s.x * s.x + s.y * s.y;
   }
-  d.pw[pix] = pw;
+  d.pw[(size_t)pw_copy(cs->flags[*it_ptr], cs->n_batches) * nn + pix] = pw;  // read by the next iteration
 }
 
 __global__ __launch_bounds__(kThreads) void k_err_reduce(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
@@ -1569,12 +1680,12 @@ PTY_DEFINE_LAUNCH(fwd_cols)
 PTY_DEFINE_LAUNCH(inv_cols)
 
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_obj_update, dim3(t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  const int pb = post_probe_blocks(t.n, t.max_k);
+  hipLaunchKernelGGL(k_obj_update, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
 }
-hipError_t launch_post(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  const int pb = post_probe_blocks(t.n, t.max_k);
-  hipLaunchKernelGGL(k_post, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+hipError_t launch_constraint(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_constraint, dim3(t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
 }
 hipError_t launch_gram(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
@@ -1594,8 +1705,8 @@ hipError_t launch_err_reduce(const CaseDesc* cases, const TableShape& t, const i
   hipLaunchKernelGGL(k_err_reduce, dim3(1, t.n_cases), dim3(kThreads), 0, s, cases, it);
   return hipGetLastError();
 }
-hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d);
+hipError_t launch_pw(const DevParams& p, const DevBufs& d, int copy, hipStream_t s) {
+  hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d, copy);
   return hipGetLastError();
 }
 hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, bool shift, int* bad,

@@ -28,7 +28,8 @@ constexpr int kColVariants = 18;
 constexpr int kFusedHalo = 5;  // halo columns of the fused middle pass (kernel sizes up to 11)
 
 // Per-iteration flags of a case.
-enum : int { FLAG_PROBE = 1, FLAG_CC = 2, FLAG_ORTHO = 4 };
+// FLAG_PW_ODD: the iteration's first batch reads copy 1 of the probe-power map (see DevBufs::pw).
+enum : int { FLAG_PROBE = 1, FLAG_CC = 2, FLAG_ORTHO = 4, FLAG_PW_ODD = 8 };
 
 struct DevParams {
   int n, k, h_obj, w_obj, n_pos;
@@ -45,7 +46,8 @@ struct DevParams {
 struct DevBufs {
   float2* obj;         // [H][W]
   float2* probe;       // [K][N][N]
-  float* pw;           // [N][N] sum_k |P_k|^2
+  float* pw;           // [2][N][N] sum_k |P_k|^2, two copies: a batch reads one (pw_copy) while its
+                       // probe update writes the other, so both updates share one launch
   const float* amp;    // [n_pos][N][N] sqrt(max(I,0)) in detector pixel order
   const int2* pos;     // [n_pos] (row, col)
   const float2* tw;    // [N] exp(-2 pi i m / N)
@@ -97,7 +99,7 @@ struct TableShape {
 
 // Kernel classes (for timing).
 enum KernelClass {
-  KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_POST, KC_GRAM, KC_EIG, KC_REMIX,
+  KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_CONSTRAINT, KC_GRAM, KC_EIG, KC_REMIX,
   KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
@@ -112,7 +114,7 @@ hipError_t launch_cols_fused(const CaseDesc* cases, const TableShape& t, int bet
 hipError_t launch_inv_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
-hipError_t launch_post(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_constraint(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 // Per-iteration launches.
 hipError_t launch_gram(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
 hipError_t launch_eig(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
@@ -124,7 +126,8 @@ hipError_t launch_iter_set(int* it, int v, hipStream_t s);
 // Init-time and debug helpers (one case, parameters by value).
 hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, bool shift, int* bad_count,
                               double* sum_part, hipStream_t s);
-hipError_t launch_pw(const DevParams& p, const DevBufs& d, hipStream_t s);
+// sum_k |P_k|^2 of the current probe into copy `copy` of d.pw
+hipError_t launch_pw(const DevParams& p, const DevBufs& d, int copy, hipStream_t s);
 hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* slots, int ns, float2* out,
                              hipStream_t s);
 

@@ -56,6 +56,8 @@ struct ptycho_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int t = 0;
+  int pw_par = 0;          // copy of db.pw that holds sum_k |P_k|^2 of the current probe
+  int pw_par_next = 0;     // the same after the staged call has run
   bool failed = false;
   std::string err;
   double inv_denom = 0.0;  // 1 / sum_n sum_q I_n
@@ -258,7 +260,9 @@ struct Timed {
     if (c->tm.used * 2 + 2 > c->tm.pool.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
+        // timing only (read after a stream synchronisation): no system-scope fence, which
+        // would add a cache write-back and invalidation to every timed launch
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return;
         c->tm.pool.push_back(e);
       }
     }
@@ -309,7 +313,7 @@ std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape
   }
   LAUNCH(tc, KC_INV_ROWS, s, launch_inv_rows(cases, sh, beta, it, s));
   LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_POST, s, launch_post(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_CONSTRAINT, s, launch_constraint(cases, sh, beta, it, s));
   return "";
 }
 
@@ -425,7 +429,7 @@ std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc
   LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, true, s));
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_delta(cases, sh, beta, it, s));
   LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_POST, s, launch_post(cases, sh, beta, it, s));
+  LAUNCH(tc, KC_CONSTRAINT, s, launch_constraint(cases, sh, beta, it, s));
   return "";
 }
 
@@ -666,7 +670,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   const int nbt = std::max(max_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
   ptycho_status st = PTYCHO_OK;
   if ((st = dev_alloc(c, &obj, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &probe, K * nn)) ||
-      (st = dev_alloc(c, &pw, nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
+      (st = dev_alloc(c, &pw, 2 * nn)) || (st = dev_alloc(c, &amp, (size_t)p.n_pos * nn)) ||
       (st = dev_alloc(c, &pos, (size_t)p.n_pos)) || (st = dev_alloc(c, &tw, (size_t)n)) ||
       (st = dev_alloc(c, &hn, (size_t)n)) || (st = dev_alloc(c, &X, (size_t)B * K * nn)) ||
       (st = dev_alloc(c, &q, (size_t)B * nn)) || (st = dev_alloc(c, &dO, (size_t)B * nn)) ||
@@ -755,7 +759,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   if ((st = dev_alloc(c, &d_bad, (size_t)p.n_pos * gx)) || (st = dev_alloc(c, &d_sum, (size_t)p.n_pos * gx)))
     return bail(st);
   INIT_TRY(launch_prepare_amp(raw, amp, n, p.n_pos, p.geometry == PTYCHO_FAR_FIELD, d_bad, d_sum, s));
-  INIT_TRY(launch_pw(dp, d, s));
+  INIT_TRY(launch_pw(dp, d, 0, s));
   std::vector<int> hb((size_t)p.n_pos * gx);
   std::vector<double> hs((size_t)p.n_pos * gx);
   INIT_TRY(hipMemcpyAsync(hb.data(), d_bad, hb.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -785,6 +789,14 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   return PTYCHO_OK;
 }
 
+// FLAG_PW_ODD for an iteration whose first batch reads probe-power copy `par`;
+// advances `par` past the iteration (every batch with probe update flips it).
+int with_pw_parity(int flags, int& par, int n_batches) {
+  if (par) flags |= FLAG_PW_ODD;
+  if (flags & FLAG_PROBE) par ^= n_batches & 1;
+  return flags;
+}
+
 // Fill the schedule of n_iter iterations of context c into its call buffers.
 static ptycho_status stage_call(ptycho_ctx* c, int32_t n_iter, const int32_t* order) {
   const int np = c->prm.n_pos;
@@ -806,6 +818,10 @@ static ptycho_status stage_call(ptycho_ctx* c, int32_t n_iter, const int32_t* or
     }
     c->call.h_flags[it] = case_flags(c->prm, c->t + 1 + it);
   }
+  int par = c->pw_par;
+  const int nb = n_batches_of(c->prm);
+  for (int it = 0; it < n_iter; ++it) c->call.h_flags[it] = with_pw_parity(c->call.h_flags[it], par, nb);
+  c->pw_par_next = par;
   return PTYCHO_OK;
 }
 
@@ -843,6 +859,7 @@ ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order
   HIP_TRY(c, hipStreamSynchronize(s));
   if (c->tm.used) harvest_timing(c);
   c->t += n_iter;
+  c->pw_par = c->pw_par_next;
   if (err_out) std::memcpy(err_out, c->call.h_err, n_iter * sizeof(float));
   for (int i = 0; i < n_iter; ++i)
     if (!std::isfinite(c->call.h_err[i])) {
@@ -899,7 +916,7 @@ ptycho_status ptycho_set_state(ptycho_ctx* c, const float* object, const float* 
     if (st == PTYCHO_OK) st = check_probe_power(c, hp.data(), hp.size());
     if (st != PTYCHO_OK) return st;
     HIP_TRY(c, hipMemcpyAsync(c->db.probe, probe, c->prm.n_modes * nn * sizeof(float2), kind_in(mem_kind), c->stream));
-    HIP_TRY(c, launch_pw(c->dp, c->db, c->stream));
+    HIP_TRY(c, launch_pw(c->dp, c->db, c->pw_par, c->stream));
   }
   if (object)
     HIP_TRY(c, hipMemcpyAsync(c->db.obj, object, (size_t)c->prm.obj_h * c->prm.obj_w * sizeof(float2),
@@ -948,7 +965,8 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   }
   // schedule of the one batch: order = idx, flags of iteration t
   std::vector<int> hidx(idx, idx + B);
-  const int flags = case_flags(c->prm, t) & ~FLAG_ORTHO;
+  int pw_par = c->pw_par;
+  const int flags = with_pw_parity(case_flags(c->prm, t) & ~FLAG_ORTHO, pw_par, 1);
   CaseDesc cd;
   fill_case(c, cd, c->d_dbg_order, c->d_dbg_flags, c->d_dbg_err);
   cd.dbg = DebugPtrs{d_psin, d_nobj, d_wobj, d_fac};
@@ -991,6 +1009,7 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   cleanup();
   if (!le.empty()) return fail(c, PTYCHO_E_HIP, le);
   if (e != hipSuccess) return fail(c, PTYCHO_E_HIP, std::string("debug step: ") + hipGetErrorString(e));
+  c->pw_par = pw_par;
   return PTYCHO_OK;
 }
 
@@ -1036,7 +1055,8 @@ ptycho_status ptycho_autotune(ptycho_ctx* c, int32_t trials, int32_t force, int3
   const int saved_variant = c->col_variant;
   ptycho_status st = (he == hipSuccess) ? stage_call(c, 1, nullptr) : PTYCHO_E_HIP;
   if (st == PTYCHO_OK) {
-    c->call.h_flags[0] = FLAG_PROBE | FLAG_CC;
+    int par = c->pw_par;  // every trial runs the first batch from the same state
+    c->call.h_flags[0] = with_pw_parity(FLAG_PROBE | FLAG_CC, par, n_batches_of(c->prm));
     for (int v = 0; v < kColVariants && err.empty(); ++v) {
       if (!col_variant_valid(n, v)) continue;
       c->col_variant = v;
@@ -1066,7 +1086,7 @@ ptycho_status ptycho_autotune(ptycho_ctx* c, int32_t trials, int32_t force, int3
   // restore the state
   (void)hipMemcpyAsync(c->db.obj, bo, no * sizeof(float2), hipMemcpyDeviceToDevice, s);
   (void)hipMemcpyAsync(c->db.probe, bp, npr * sizeof(float2), hipMemcpyDeviceToDevice, s);
-  (void)launch_pw(c->dp, c->db, s);
+  (void)launch_pw(c->dp, c->db, c->pw_par, s);
   hipError_t fin = hipStreamSynchronize(s);
   (void)hipFree(bo);
   (void)hipFree(bp);
@@ -1279,6 +1299,13 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
       splitmix_perm(c->prm.seed, c->t + 1 + it, np, g->call.h_order + off[i] + (size_t)it * np);
       g->call.h_flags[(size_t)i * n_iter + it] = case_flags(c->prm, c->t + 1 + it);
     }
+    int par = c->pw_par;
+    const int nb = n_batches_of(c->prm);
+    for (int it = 0; it < n_iter; ++it) {
+      int& f = g->call.h_flags[(size_t)i * n_iter + it];
+      f = with_pw_parity(f, par, nb);
+    }
+    c->pw_par_next = par;
     max_nb = std::max(max_nb, n_batches_of(c->prm));
   }
   for (auto& tb : g->tables)
@@ -1315,6 +1342,7 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
   for (int i = 0; i < nc; ++i) {
     ptycho_ctx* c = g->ctx[i];
     c->t += n_iter;
+    c->pw_par = c->pw_par_next;
     for (int it = 0; it < n_iter; ++it)
       if (!std::isfinite(g->call.h_err[(size_t)i * n_iter + it]) && !c->failed) {
         c->failed = true;

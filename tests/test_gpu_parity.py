@@ -172,6 +172,31 @@ def test_determinism_and_resume():
         np.testing.assert_array_equal(e3, runs[0][2][2:3])
 
 
+def test_split_calls_match_one_call():
+    """Iterations spread over several calls (eager and graph-replayed) give bitwise the
+    result of one call: 25 positions in batches of 4 (an odd number of batches per
+    iteration), the probe frozen for the first two iterations, a constraint window."""
+    import paper_2406_06640_amd as P
+    s = make_case(n=32, k=2, obj=(80, 80), n_side=5, step=8, seed=23)
+    cp, _ = params_pair(s, batch=4, probe_update_start=3, cc_start=2, cc_end=3)
+    _announce("split calls n=32 K=2 odd batch count")
+    o32, p32 = state32(s)
+    orders = _orders(7, 0, 5, len(s["positions"]))
+    with P.Reconstruction(cp, s["intensities"], s["positions"], p32, o32) as r:
+        e_all = r.iterate(5, orders)
+        ref = (r.object(), r.probe())
+    for graph, cuts in ((False, (1, 2, 3, 4)), (True, (2,)), (True, (1, 3))):
+        with P.Reconstruction(cp, s["intensities"], s["positions"], p32, o32) as r:
+            r.set_graph(graph)
+            errs, lo = [], 0
+            for hi in list(cuts) + [5]:
+                errs.append(r.iterate(hi - lo, orders[lo:hi]))
+                lo = hi
+            np.testing.assert_array_equal(r.object(), ref[0])
+            np.testing.assert_array_equal(r.probe(), ref[1])
+            np.testing.assert_array_equal(np.concatenate(errs), e_all)
+
+
 def test_library_order_generator_matches_explicit():
     import paper_2406_06640_amd as P
     s = make_case(n=32, obj=(72, 72), n_side=4, step=8, seed=4)
