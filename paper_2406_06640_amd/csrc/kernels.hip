@@ -1390,23 +1390,33 @@ __global__ __launch_bounds__(kThreads) void k_remix(const CaseDesc* __restrict__
   d.pw[(size_t)pw_copy(cs->flags[*it_ptr], cs->n_batches) * nn + pix] = pw;  // read by the next iteration
 }
 
-__global__ __launch_bounds__(kThreads) void k_err_reduce(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
-  __shared__ double red[kThreads / 64];
+// One 1024-thread block per case (the partials of a whole iteration are few
+// but one pass of 256 threads would wait on ~12 rounds of dependent loads).
+constexpr int kErrThreads = 1024;
+__global__ __launch_bounds__(kErrThreads) void k_err_reduce(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
+  __shared__ double red[kErrThreads / 64];
   const CaseDesc* cs = cases + blockIdx.y;
   const double* part = global_bufs(cs->d).err_part;
   const int count = cs->n_err_part;
   // eight independent partial sums per thread (eight loads in flight), combined in a fixed order
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < count; i += 8 * kThreads) {
+  for (int i = threadIdx.x; i < count; i += 8 * kErrThreads) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int j = i + u * kThreads;
+      const int j = i + u * kErrThreads;
       if (j < count) acc[u] += part[j];
     }
   }
   double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  s = block_sum_d(s, red);
-  if (threadIdx.x == 0) cs->err_out[*it_ptr] = (float)(s * cs->inv_denom);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kErrThreads / 64; ++w) t += red[w];
+    cs->err_out[*it_ptr] = (float)(t * cs->inv_denom);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1702,7 +1712,7 @@ hipError_t launch_remix(const CaseDesc* cases, const TableShape& t, const int* i
   return hipGetLastError();
 }
 hipError_t launch_err_reduce(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_err_reduce, dim3(1, t.n_cases), dim3(kThreads), 0, s, cases, it);
+  hipLaunchKernelGGL(k_err_reduce, dim3(1, t.n_cases), dim3(kErrThreads), 0, s, cases, it);
   return hipGetLastError();
 }
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, int copy, hipStream_t s) {
