@@ -300,7 +300,8 @@ void harvest_timing(ptycho_ctx* c) {
     if (e_ != hipSuccess) return std::string(kKernelNames[cls]) + ": " + hipGetErrorString(e_); \
   } while (0)
 
-// The six launches of batch `beta` for every case of a table.
+// The seven launches of batch `beta` for every case of a table (five when the
+// fused middle pass replaces fwd_cols, modulus_factor and inv_cols).
 std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
                          hipStream_t s) {
   LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
