@@ -53,6 +53,25 @@ def measured_traffic(kernel_class):
     return int(m.group(1)) if m else None
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate in GB/s (bytes read + bytes written per second) of a plain
+    `nbytes` tensor copy, timed with HIP events: the achievable HBM rate the kernels can be
+    compared with beside the nominal peak."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def per_slot_bytes(name, n, k):
     """Algorithmic HBM bytes one batch slot (one scan position) costs in kernel `name`,
     counting each frame read or written at its pass boundary once (complex64 = 8 B,
@@ -352,6 +371,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_bandwidth(torch, dev)
     spec, s, gen_s = build_workload()
     print(f"[bench] workload generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
     n, k, n_pos = s["n"], s["k"], len(s["positions"])
@@ -403,6 +423,7 @@ def main():
         achieved = bytes_per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+                "measured_copy_peak": round(copy_gbs, 1), "frac_of_measured_copy": round(achieved / copy_gbs, 4),
                 "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)}
     out = {
         "metric": "mode-pattern updates/s",
