@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
-PMC_PROFILE = os.path.join(ROOT, "profiles", "c2_far256_k4_b32_pmc_traffic.txt")
+PMC_PROFILE = os.path.join(ROOT, "profiles", "far256_k4_b32_pmc_traffic.txt")
 KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "fft_lds.hpp", "dft_mfma.hip"]
 
 
@@ -90,9 +90,9 @@ def per_slot_bytes(name, n, k):
 
 def build_workload(n_pos=None):
     import datagen
-    spec = datagen.CONFIGS["c2"]
+    spec = datagen.CONFIGS["far256_k4"]
     t0 = time.time()
-    s = datagen.make_scan(spec, 1002, n_pos=n_pos)
+    s = datagen.make_scan(spec, spec["seed"], n_pos=n_pos)
     return spec, s, time.time() - t0
 
 
@@ -137,7 +137,7 @@ def warm_start_leg(n_iter):
     from paper_2406_06640_amd import evaluate as E
     scans = []
     for i, sd in enumerate(E.SIGMA_SWEEP):
-        spec = dict(datagen.CONFIGS["c1"])
+        spec = dict(datagen.CONFIGS["far64"])
         spec.update(sigma_data=sd)
         scans.append(datagen.make_scan(spec, [1005, 7, i]))
     net, report = E.load_warm_start()
@@ -177,14 +177,14 @@ def _time_iterations(P, torch, s, cp, steps, graph=True, autotune=True):
     return 1e3 * wall / steps, variant, float(errs[-1])
 
 
-def c3_leg(steps=5):
+def near_field_leg(steps=5):
     """Near field: object 1536^2, frames 512^2, 15 x 15 positions at 60 +- 10 px, K = 8, sigma 1.5, B = 8."""
     import torch
     import datagen
     import paper_2406_06640_amd as P
-    spec = datagen.CONFIGS["c3"]
+    spec = datagen.CONFIGS["near512_k8"]
     t0 = time.time()
-    s = datagen.make_scan(spec, 1003)
+    s = datagen.make_scan(spec, spec["seed"])
     gen = time.time() - t0
     cp = make_params(P, s, spec, spec["batch"])
     cp.fresnel_px = float(s["fresnel_px"])
@@ -207,7 +207,7 @@ def paper_shapes_leg(steps=5):
         n = 1024
         extent = 9 * step + n + 2
         side = int(np.ceil(extent / 16.0) * 16)
-        spec = dict(datagen.CONFIGS["c1"])
+        spec = dict(datagen.CONFIGS["far64"])
         spec.update(geometry=geometry, obj=(side, side), n=n, n_side=10, step=step, jitter=1, k=1,
                     powers=(1.0,), radius=n // 4, defocus=1.0 if geometry == 0 else 0.0, sigma_data=1.0,
                     counts=1e6, fresnel_px=4.13e-3 if geometry == 1 else 0.0, sigma=1.0, batch=1)
@@ -230,7 +230,7 @@ def paper_shapes_leg(steps=5):
     return out
 
 
-def c4_leg(iters):
+def batched_leg(iters):
     """The 64-case batched workload (N in {64,128,192,256}, 100-2500 positions, 1-8 modes, batch 32,
     seeds [1004, i]; patterns made on the GPU): every case alone (autotuned, graph replay) against
     all cases as one group (graph replay), same final states required bitwise; and the BF16
@@ -247,7 +247,7 @@ def c4_leg(iters):
         cases.append((sp, gpu_synth.make_scan(sp, sp["seed_key"])))
     torch.cuda.synchronize()
     gen_s = time.time() - t0
-    print(f"[bench] c4 generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    print(f"[bench] 64-case workload generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
     def make(sp, s, dft=False):
         h, w = s["obj0"].shape
@@ -342,11 +342,11 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the time-to-NMSE comparison of the plain and the learned + batched start")
     ap.add_argument("--warm-start-iterations", type=int, default=30)
-    ap.add_argument("--c4", action="store_true",
+    ap.add_argument("--batched", action="store_true",
                     help="also run the 64-case batched workload: group launch vs the cases one by one, "
                          "and the BF16 matrix-core DFT path")
-    ap.add_argument("--c4-iterations", type=int, default=3)
-    ap.add_argument("--c3", action="store_true", help="also time the near-field 1536^2 / 512^2 / K=8 workload")
+    ap.add_argument("--batched-iterations", type=int, default=3)
+    ap.add_argument("--near-field", action="store_true", help="also time the near-field 1536^2 / 512^2 / K=8 workload")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="also time the paper's own scan shapes (100 patterns of 1024^2, one mode, far and near "
                          "field) for comparison with its per-iteration times")
@@ -451,15 +451,15 @@ def main():
     if not args.no_warm_start:
         print("[bench] warm-start sweep (time to NMSE, plain vs learned + batched)", file=sys.stderr, flush=True)
         out["time_to_nmse"] = warm_start_leg(args.warm_start_iterations)
-    if args.c3:
+    if args.near_field:
         print("[bench] near-field workload", file=sys.stderr, flush=True)
-        out["c3"] = c3_leg()
+        out["near_field"] = near_field_leg()
     if args.paper_shapes:
         print("[bench] paper-shape scans", file=sys.stderr, flush=True)
         out["paper_shapes"] = paper_shapes_leg()
-    if args.c4:
+    if args.batched:
         print("[bench] 64-case batched workload", file=sys.stderr, flush=True)
-        out["c4"] = c4_leg(args.c4_iterations)
+        out["batched"] = batched_leg(args.batched_iterations)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, spec, args.batch, args.cpu_batches)

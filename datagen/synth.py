@@ -244,16 +244,16 @@ def initial_guess(obj_shape, n, k, radius, intensities, defocus=0.0):
 CONFIGS = {
     # far field, 64^2 frames, 10x10 raster at 8 px; object enlarged to 144^2 so the
     # scan extent 9*8 + 64 + 2 fits
-    "c1": dict(geometry=0, obj=(144, 144), n=64, n_side=10, step=8, jitter=1, k=1, powers=(1.0,),
+    "far64": dict(seed=1001, geometry=0, obj=(144, 144), n=64, n_side=10, step=8, jitter=1, k=1, powers=(1.0,),
                radius=16, defocus=1.0, sigma_data=1.0, counts=1e5, wavelengths=(1.0,),
                sigma=1.0, batch=1, iterations=50, screen=None, fresnel_px=0.0),
     # far field, 256^2 frames, 40x40 raster at 16 px, 4 modes, 5 wavelengths +-2.5 %
-    "c2": dict(geometry=0, obj=(1024, 1024), n=256, n_side=40, step=16, jitter=1, k=4,
+    "far256_k4": dict(seed=1002, geometry=0, obj=(1024, 1024), n=256, n_side=40, step=16, jitter=1, k=4,
                powers=(0.6, 0.25, 0.1, 0.05), radius=64, defocus=1.0, sigma_data=2.0, counts=1e6,
                wavelengths=tuple(1.0 / (1.0 + s) for s in (-0.025, -0.0125, 0.0, 0.0125, 0.025)),
                sigma=2.0, batch=32, iterations=200, screen=None, fresnel_px=0.0),
     # near field, 512^2 frames, 15x15 raster at 60 +- 10 px, 8 modes, F_px = 20 / 70^2
-    "c3": dict(geometry=1, obj=(1536, 1536), n=512, n_side=15, step=60, jitter=10, k=8,
+    "near512_k8": dict(seed=1003, geometry=1, obj=(1536, 1536), n=512, n_side=15, step=60, jitter=10, k=8,
                powers=tuple(2.0 ** -i for i in range(8)), radius=70, defocus=0.0, sigma_data=1.5,
                counts=1e6, wavelengths=(1.0,), sigma=1.5, batch=8, iterations=100, screen=2.0,
                fresnel_px=20.0 / 70.0 ** 2),

@@ -20,7 +20,7 @@ def rel_l2(a, b):
 
 def make_case(n=32, k=1, geometry=0, obj=(80, 80), n_side=4, step=8, radius=None, seed=11,
               sigma_data=1.0, fresnel_px=None, wavelengths=(1.0,), jitter=1, n_pos=None, screen=None):
-    spec = dict(datagen.CONFIGS["c1"])
+    spec = dict(datagen.CONFIGS["far64"])
     radius = radius if radius is not None else max(n // 4, 2)
     if geometry == 1 and fresnel_px is None:
         fresnel_px = 20.0 / float(radius * radius)

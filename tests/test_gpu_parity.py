@@ -212,7 +212,7 @@ def test_library_order_generator_matches_explicit():
         np.testing.assert_array_equal(r.object(), a)
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c3"])
+@pytest.mark.parametrize("cfg", ["far256_k4", "near512_k8"])
 def test_full_size_batch_step(cfg):
     """One batch at the full frame size and batch size of the 1024^2 far-field
     (256^2 frames, K = 4, B = 32, 5-wavelength data) and 1536^2 near-field
@@ -220,7 +220,7 @@ def test_full_size_batch_step(cfg):
     import datagen
     spec = datagen.CONFIGS[cfg]
     B = spec["batch"]
-    s = datagen.make_scan(spec, 1000 + int(cfg[1]), n_pos=2 * B)
+    s = datagen.make_scan(spec, spec["seed"], n_pos=2 * B)
     cp, op = params_pair(s, batch=B, cc_start=1, cc_end=10)
     idx = list(range(1, 2 * B, 2))
     _announce(f"full-size step {cfg} n={cp.n} K={cp.n_modes} B={B}")

@@ -29,7 +29,7 @@ def _announce(msg):
 def _scans():
     out = []
     for i, sd in enumerate(SIGMAS):
-        spec = dict(datagen.CONFIGS["c1"])
+        spec = dict(datagen.CONFIGS["far64"])
         spec.update(sigma_data=sd)
         out.append(datagen.make_scan(spec, [1005, 7, i]))
     return out

@@ -9,7 +9,7 @@ import oracle as ora
 
 
 def _small(sigma_data):
-    spec = dict(datagen.CONFIGS["c1"])
+    spec = dict(datagen.CONFIGS["far64"])
     spec.update(obj=(64, 64), n=32, n_side=5, step=6, radius=9, jitter=1, sigma_data=sigma_data)
     return spec, datagen.make_scan(spec, 7, noise=False, probe_known=True)
 

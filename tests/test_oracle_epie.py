@@ -128,7 +128,7 @@ def test_permutation_is_deterministic_permutation():
 def test_iteration_error_decreases_noise_free(rng):
     """Data error E_t of a noise-free, fully coherent scan falls as ePIE iterates."""
     import datagen
-    spec = dict(datagen.CONFIGS["c1"])
+    spec = dict(datagen.CONFIGS["far64"])
     spec.update(obj=(48, 48), n=16, n_side=4, step=6, radius=5, jitter=0, sigma_data=0.0)
     s = datagen.make_scan(spec, 5, noise=False, probe_known=True)
     params = ora.Params(n=16, sigma1=0.0, sigma2=0.0, probe_update_start=1000, batch=1)

@@ -34,7 +34,7 @@ def test_scaled_dft_matches_chirp_z(rng):
 
 def test_wavelength_scales_match_broadband_config():
     got = fm.wavelength_scales(0.05)
-    np.testing.assert_allclose(got, datagen.CONFIGS["c2"]["wavelengths"], rtol=1e-14)
+    np.testing.assert_allclose(got, datagen.CONFIGS["far256_k4"]["wavelengths"], rtol=1e-14)
     np.testing.assert_allclose(fm.wavelength_scales(0.0), np.ones(5))
 
 
