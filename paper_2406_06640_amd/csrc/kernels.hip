@@ -262,14 +262,25 @@ struct SideScratch;
 __device__ void side_job(const DevParams& p, const DevBufsG& d, int pwc, const int* slots, int ns, int job,
                          bool with_v, SideScratch& sc);
 
+// Workgroups are dispatched to the 8 XCDs round-robin (XCD = block index mod 8),
+// each with its own L2.  Column tiles narrower than a 128-byte line (C < 16)
+// share every line with their neighbour, so tiles 2m and 2m + 1 go to blocks that
+// land on the same XCD in consecutive rounds: the second half of each line is an
+// L2 hit instead of a second HBM fetch.  paired_tile is a permutation of each
+// group of 16 block indices; launches round their grids up to 16 blocks.
+__device__ __forceinline__ int paired_tile(int g) { return 2 * ((g >> 4) * 8 + (g & 7)) + ((g >> 3) & 1); }
+static inline int paired_blocks(int tiles) { return (tiles + 15) / 16 * 16; }
+
 // Mode-parallel launches (MP) give every (slot, line block, mode) its own
-// workgroup.  Workgroups are dispatched to the 8 XCDs round-robin, so the modes
-// of one (slot, line block) are numbered g, g + 8, g + 16, ...: they land on the
-// same XCD one after another and share its L2 for the inputs they have in common.
+// workgroup.  The modes of one (slot, line block) are numbered g, g + 8,
+// g + 16, ...: they land on the same XCD one after another and share its L2 for
+// the inputs they have in common; the u-th tile an XCD receives is paired with
+// its neighbour as in paired_tile.
 __device__ __forceinline__ void mp_decode(int g, int km, int& tile, int& k0) {
   const int r = g >> 3;
   k0 = r % km;
-  tile = (r / km) * 8 + (g & 7);
+  const int u = r / km;
+  tile = 2 * ((u >> 1) * 8 + (g & 7)) + (u & 1);
 }
 
 // Row pass 1: psi = o_b P_k and the 1D transform along x.  Serial launches walk
@@ -434,7 +445,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
   extern __shared__ float2 sm[];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
-  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  const int pt = paired_tile(blockIdx.x);
+  const int b = pt / GX, bx = pt % GX;
   if (b >= bt.ns) return;
   const DevParams& p = bt.cs->p;
   const DevBufsG d = global_bufs(bt.cs->d);
@@ -594,8 +606,9 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(const CaseDesc* __restric
     bx = tile % GX;
     if (b >= bt.ns || k0 >= p.k) return;
   } else {
-    b = blockIdx.x / GX;
-    bx = blockIdx.x % GX;
+    const int pt = paired_tile(blockIdx.x);
+    b = pt / GX;
+    bx = pt % GX;
     if (b >= bt.ns) return;
   }
   const DevBufsG d = global_bufs(bt.cs->d);
@@ -666,7 +679,8 @@ __global__ __launch_bounds__(kThreads) void k_cols_fused(const CaseDesc* __restr
   __shared__ float sgx[kMaxHalf + 1], sgy[kMaxHalf + 1];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
-  const int b = blockIdx.x / GX, bx = blockIdx.x % GX;
+  const int pt = paired_tile(blockIdx.x);
+  const int b = pt / GX, bx = pt % GX;
   if (b >= bt.ns) return;
   const DevParams& p = bt.cs->p;
   const DevBufsG d = global_bufs(bt.cs->d);
@@ -1563,7 +1577,7 @@ int max_err_slots(int n) {
 int n_obj_tiles(const DevParams& p) { return tiles_of(p); }
 int n_probe_blocks(int n) { return n_probe_blocks_dev(n); }
 
-static int mp_blocks(int tiles, int km) { return ((tiles + 7) / 8) * 8 * km; }
+static int mp_blocks(int tiles, int km) { return paired_blocks(tiles) * km; }
 
 template <int N, bool NEAR>
 static hipError_t fwd_rows_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
@@ -1596,7 +1610,7 @@ template <int N, bool NEAR, int V>
 static hipError_t fwd_cols_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int C = ColW<N, V>::C;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, C, true>::ELEMS);
-  hipLaunchKernelGGL((k_fwd_cols<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
+  hipLaunchKernelGGL((k_fwd_cols<N, NEAR, C>), dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s,
                      cases, beta, it);
   return hipGetLastError();
 }
@@ -1605,7 +1619,7 @@ static hipError_t cols_fused_v(const CaseDesc* cases, const TableShape& t, int b
   constexpr int C = ColW<N, V>::C;
   constexpr int NL = C + 2 * kFusedHalo;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, NL, true>::ELEMS);
-  hipLaunchKernelGGL((k_cols_fused<N, NEAR, C>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s, cases,
+  hipLaunchKernelGGL((k_cols_fused<N, NEAR, C>), dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s, cases,
                      beta, it);
   return hipGetLastError();
 }
@@ -1635,7 +1649,7 @@ static hipError_t inv_cols_v(const CaseDesc* cases, const TableShape& t, int bet
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_inv_cols<N, NEAR, C, false>), dim3((N / C) * t.max_batch, t.n_cases), dim3(kThreads), sh, s,
+  hipLaunchKernelGGL((k_inv_cols<N, NEAR, C, false>), dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s,
                      cases, beta, it, 1);
   return hipGetLastError();
 }
