@@ -60,8 +60,9 @@ def state32(s):
     return o, p
 
 
-def gpu_step(s, cp, idx, t, obj=None, probe=None):
-    """One debug step on a fresh context; returns the captures and the updated state."""
+def gpu_step(s, cp, idx, t, obj=None, probe=None, variant=None):
+    """One debug step on a fresh context (launch variant `variant` if given); returns the
+    captures and the updated state."""
     import paper_2406_06640_amd as P
 
     o32, p32 = state32(s)
@@ -78,6 +79,8 @@ def gpu_step(s, cp, idx, t, obj=None, probe=None):
                v_probe=np.zeros((n, n), np.float32))
     rec = P.Reconstruction(cp, s["intensities"], s["positions"], p32, o32)
     try:
+        if variant is not None:
+            rec.set_variant(variant)
         P.ptycho_debug_step(rec.ctx, idx, t, **cap)
         cap["O"] = rec.object()
         cap["P"] = rec.probe()

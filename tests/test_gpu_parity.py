@@ -212,18 +212,21 @@ def test_library_order_generator_matches_explicit():
         np.testing.assert_array_equal(r.object(), a)
 
 
-@pytest.mark.parametrize("cfg", ["far256_k4", "near512_k8"])
-def test_full_size_batch_step(cfg):
+@pytest.mark.parametrize("cfg,variant", [("far256_k4", None), ("far256_k4", 10), ("near512_k8", None),
+                                         ("near512_k8", 10)])
+def test_full_size_batch_step(cfg, variant):
     """One batch at the full frame size and batch size of the 1024^2 far-field
     (256^2 frames, K = 4, B = 32, 5-wavelength data) and 1536^2 near-field
-    (512^2 frames, K = 8, B = 8) workloads, constraint window on."""
+    (512^2 frames, K = 8, B = 8) workloads, constraint window on; in the default
+    launch configuration and in variant 10 (mode-parallel first row pass and
+    inverse column pass), the one the autotuner picks for both in the benchmark."""
     import datagen
     spec = datagen.CONFIGS[cfg]
     B = spec["batch"]
     s = datagen.make_scan(spec, spec["seed"], n_pos=2 * B)
     cp, op = params_pair(s, batch=B, cc_start=1, cc_end=10)
     idx = list(range(1, 2 * B, 2))
-    _announce(f"full-size step {cfg} n={cp.n} K={cp.n_modes} B={B}")
-    gc, o32, p32 = gpu_step(s, cp, idx, 1)
+    _announce(f"full-size step {cfg} n={cp.n} K={cp.n_modes} B={B} variant={variant}")
+    gc, o32, p32 = gpu_step(s, cp, idx, 1, variant=variant)
     oc = oracle_step(s, op, idx, 1, o32, p32)
     _compare_step(gc, oc, cp)
