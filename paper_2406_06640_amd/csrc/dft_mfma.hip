@@ -319,11 +319,11 @@ static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inver
   DftPlanes F{planes};
   const int rows = frames * N;
   if (!inverse) {
-    hipLaunchKernelGGL((k_dft_right<N, false>), dim3(rows / 16), dim3(256), 0, s, X, F, rows);
-    hipLaunchKernelGGL((k_dft_left<N, false>), dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, false>, dim3(rows / 16), dim3(256), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, false>, dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
   } else {
-    hipLaunchKernelGGL((k_dft_left<N, true>), dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
-    hipLaunchKernelGGL((k_dft_right<N, true>), dim3(rows / 16), dim3(256), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, true>, dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, true>, dim3(rows / 16), dim3(256), 0, s, X, F, rows);
   }
   return hipGetLastError();
 }
@@ -341,27 +341,27 @@ hipError_t launch_dft2(float2* X, const void* planes, int n, int frames, bool in
 static int pix_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
 
 hipError_t launch_dft_side(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft_side, dim3(t.max_side_jobs, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  pty_launch(k_dft_side, dim3(t.max_side_jobs, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
 }
 hipError_t launch_dft_exit(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft_exit, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
+  pty_launch(k_dft_exit, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
                      it);
   return hipGetLastError();
 }
 hipError_t launch_dft_modsum(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft_modsum, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
+  pty_launch(k_dft_modsum, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
                      it);
   return hipGetLastError();
 }
 hipError_t launch_dft_blur_apply(const CaseDesc* cases, const TableShape& t, int beta, const int* it,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_dft_blur_apply, dim3(dft_err_slots(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s,
+  pty_launch(k_dft_blur_apply, dim3(dft_err_slots(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s,
                      cases, beta, it);
   return hipGetLastError();
 }
 hipError_t launch_dft_delta(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft_delta, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
+  pty_launch(k_dft_delta, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
                      it);
   return hipGetLastError();
 }

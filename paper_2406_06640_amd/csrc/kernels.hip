@@ -25,11 +25,30 @@
 
 #include "fft_lds.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace pty {
 
 const char* const kKernelNames[KC_COUNT] = {
     "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_probe_update", "complex_constraint",
     "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor", "cols_fused"};
+
+LaunchEvents& launch_events() {
+  thread_local LaunchEvents ev;
+  return ev;
+}
+
+// Every kernel of this library is launched through here (see LaunchEvents).
+template <class... P, class... A>
+static inline void pty_launch(void (*kernel)(P...), dim3 grid, dim3 block, size_t shmem, hipStream_t s, A... args) {
+  LaunchEvents& ev = launch_events();
+  if (ev.stop) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, s, ev.start, ev.stop, 0u, static_cast<P>(args)...);
+    ev.start = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, static_cast<P>(args)...);
+  }
+}
 
 constexpr int kThreads = 256;
 
@@ -1588,13 +1607,13 @@ static hipError_t fwd_rows_t(const CaseDesc* cases, const TableShape& t, int bet
   if constexpr (TunedCols<N>::value) {
     if (var_mp_rows(t.col_variant)) {
       const int main = mp_blocks(gx * t.max_batch, t.max_k);
-      hipLaunchKernelGGL((k_fwd_rows<N, NEAR, true>), dim3(main + t.max_side_jobs, t.n_cases), dim3(kThreads), sh, s,
+      pty_launch(k_fwd_rows<N, NEAR, true>, dim3(main + t.max_side_jobs, t.n_cases), dim3(kThreads), sh, s,
                          cases, beta, it, t.max_k, main);
       return hipGetLastError();
     }
   }
   const int side_rows = (t.max_side_jobs + gx - 1) / gx;
-  hipLaunchKernelGGL((k_fwd_rows<N, NEAR, false>), dim3(gx * (t.max_batch + side_rows), t.n_cases), dim3(kThreads),
+  pty_launch(k_fwd_rows<N, NEAR, false>, dim3(gx * (t.max_batch + side_rows), t.n_cases), dim3(kThreads),
                      sh, s, cases, beta, it, 1, 0);
   return hipGetLastError();
 }
@@ -1602,7 +1621,7 @@ template <int N, bool NEAR>
 static hipError_t inv_rows_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
-  hipLaunchKernelGGL((k_inv_rows<N, NEAR>), dim3((N / L) * t.max_batch, t.n_cases), dim3(kThreads), sh, s, cases,
+  pty_launch(k_inv_rows<N, NEAR>, dim3((N / L) * t.max_batch, t.n_cases), dim3(kThreads), sh, s, cases,
                      beta, it);
   return hipGetLastError();
 }
@@ -1610,7 +1629,7 @@ template <int N, bool NEAR, int V>
 static hipError_t fwd_cols_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int C = ColW<N, V>::C;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, C, true>::ELEMS);
-  hipLaunchKernelGGL((k_fwd_cols<N, NEAR, C>), dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s,
+  pty_launch(k_fwd_cols<N, NEAR, C>, dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s,
                      cases, beta, it);
   return hipGetLastError();
 }
@@ -1619,7 +1638,7 @@ static hipError_t cols_fused_v(const CaseDesc* cases, const TableShape& t, int b
   constexpr int C = ColW<N, V>::C;
   constexpr int NL = C + 2 * kFusedHalo;
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, NL, true>::ELEMS);
-  hipLaunchKernelGGL((k_cols_fused<N, NEAR, C>), dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s, cases,
+  pty_launch(k_cols_fused<N, NEAR, C>, dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s, cases,
                      beta, it);
   return hipGetLastError();
 }
@@ -1634,7 +1653,7 @@ static hipError_t cols_fused_t(const CaseDesc* cases, const TableShape& t, int b
 }
 template <int N>
 static hipError_t factor_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL((k_factor<N>), dim3((N / Cfg<N>::ROWS) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases,
+  pty_launch(k_factor<N>, dim3((N / Cfg<N>::ROWS) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases,
                      beta, it);
   return hipGetLastError();
 }
@@ -1644,12 +1663,12 @@ static hipError_t inv_cols_v(const CaseDesc* cases, const TableShape& t, int bet
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, C, true>::ELEMS);
   if constexpr (TunedCols<N>::value) {
     if (var_mp_cols(t.col_variant)) {
-      hipLaunchKernelGGL((k_inv_cols<N, NEAR, C, true>), dim3(mp_blocks((N / C) * t.max_batch, t.max_k), t.n_cases),
+      pty_launch(k_inv_cols<N, NEAR, C, true>, dim3(mp_blocks((N / C) * t.max_batch, t.max_k), t.n_cases),
                          dim3(kThreads), sh, s, cases, beta, it, t.max_k);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_inv_cols<N, NEAR, C, false>), dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s,
+  pty_launch(k_inv_cols<N, NEAR, C, false>, dim3(paired_blocks((N / C) * t.max_batch), t.n_cases), dim3(kThreads), sh, s,
                      cases, beta, it, 1);
   return hipGetLastError();
 }
@@ -1705,37 +1724,37 @@ PTY_DEFINE_LAUNCH(inv_cols)
 
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   const int pb = post_probe_blocks(t.n, t.max_k);
-  hipLaunchKernelGGL(k_obj_update, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  pty_launch(k_obj_update, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
 }
 hipError_t launch_constraint(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_constraint, dim3(t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  pty_launch(k_constraint, dim3(t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
 }
 hipError_t launch_gram(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
   const int pairs = t.max_k * (t.max_k + 1) / 2;
-  hipLaunchKernelGGL(k_gram, dim3(kGramBlocks * pairs, t.n_cases), dim3(kThreads), 0, s, cases, it);
+  pty_launch(k_gram, dim3(kGramBlocks * pairs, t.n_cases), dim3(kThreads), 0, s, cases, it);
   return hipGetLastError();
 }
 hipError_t launch_eig(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig, dim3(1, t.n_cases), dim3(64), 0, s, cases, it);
+  pty_launch(k_eig, dim3(1, t.n_cases), dim3(64), 0, s, cases, it);
   return hipGetLastError();
 }
 hipError_t launch_remix(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_remix, dim3(n_probe_blocks(t.n), t.n_cases), dim3(kThreads), 0, s, cases, it);
+  pty_launch(k_remix, dim3(n_probe_blocks(t.n), t.n_cases), dim3(kThreads), 0, s, cases, it);
   return hipGetLastError();
 }
 hipError_t launch_err_reduce(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_err_reduce, dim3(1, t.n_cases), dim3(kErrThreads), 0, s, cases, it);
+  pty_launch(k_err_reduce, dim3(1, t.n_cases), dim3(kErrThreads), 0, s, cases, it);
   return hipGetLastError();
 }
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, int copy, hipStream_t s) {
-  hipLaunchKernelGGL(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d, copy);
+  pty_launch(k_pw, dim3(n_probe_blocks(p.n)), dim3(kThreads), 0, s, p, d, copy);
   return hipGetLastError();
 }
 hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, bool shift, int* bad,
                               double* sum_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare_amp, dim3(8, n_pos), dim3(kThreads), 0, s, inten, amp, n, shift ? 1 : 0, bad,
+  pty_launch(k_prepare_amp, dim3(8, n_pos), dim3(kThreads), 0, s, inten, amp, n, shift ? 1 : 0, bad,
                      sum_part);
   return hipGetLastError();
 }
@@ -1746,16 +1765,16 @@ __global__ void k_iter_set(int* it, int v) {
   if (threadIdx.x == 0) *it = v;
 }
 hipError_t launch_iter_advance(int* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, it);
+  pty_launch(k_iter_advance, dim3(1), dim3(64), 0, s, it);
   return hipGetLastError();
 }
 hipError_t launch_iter_set(int* it, int v, hipStream_t s) {
-  hipLaunchKernelGGL(k_iter_set, dim3(1), dim3(64), 0, s, it, v);
+  pty_launch(k_iter_set, dim3(1), dim3(64), 0, s, it, v);
   return hipGetLastError();
 }
 hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* slots, int ns, float2* out,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_exit_waves, dim3(n_probe_blocks(p.n), ns), dim3(kThreads), 0, s, p, d, slots, ns, out);
+  pty_launch(k_exit_waves, dim3(n_probe_blocks(p.n), ns), dim3(kThreads), 0, s, p, d, slots, ns, out);
   return hipGetLastError();
 }
 

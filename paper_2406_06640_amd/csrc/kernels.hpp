@@ -104,6 +104,15 @@ enum KernelClass {
 };
 extern const char* const kKernelNames[KC_COUNT];
 
+// Per-kernel timing events for the launcher call in progress on this thread
+// (set by the runtime's timing, empty otherwise): the first kernel the call
+// launches records `start` when it starts, every kernel records `stop` when it
+// ends, so the pair spans the call's kernels without separate event packets.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& launch_events();
+
 // Batch launches for batch index `beta` of the call's current iteration, which
 // the kernels read from the device counter `it` (so that a captured iteration
 // graph can be replayed unchanged).

@@ -271,10 +271,17 @@ struct Timed {
     c->tm.cls.resize(c->tm.used + 1);
     c->tm.cls[c->tm.used] = k;
     c->tm.used++;
-    (void)hipEventRecord(start, s);
+    // recorded by the launched kernels themselves (LaunchEvents)
+    launch_events() = LaunchEvents{start, stop};
   }
   ~Timed() {
-    if (stop) (void)hipEventRecord(stop, s);
+    if (!stop) return;
+    LaunchEvents& ev = launch_events();
+    if (ev.start) {  // nothing was launched: an empty interval
+      (void)hipEventRecord(ev.start, s);
+      (void)hipEventRecord(stop, s);
+    }
+    ev = LaunchEvents{};
   }
 };
 
