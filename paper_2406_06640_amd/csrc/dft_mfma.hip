@@ -47,11 +47,14 @@ __device__ __forceinline__ floatx4 mma3(bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 
   return c;
 }
 
-// DFT table planes [4][N][N] (re_hi, re_lo, im_hi, im_lo) of F, row-major [u][x].
+// DFT table planes (re_hi, re_lo, im_hi, im_lo) of F in MFMA fragment order:
+// F[u][x] at [plane][u / 16][x / 32][16 ((x % 32) / 8) + u % 16][x % 8].  frag()
+// returns lane `lane`'s 8 values of the 16 x 32 fragment rows 16 rt.., columns 32 kc..
+// (row 16 rt + lane % 16, columns 32 kc + 8 (lane / 16) + 0..7): a wave reads 1 KB in a row.
 struct DftPlanes {
   const __bf16* p;
-  __device__ __forceinline__ bf16x8 load(int plane, int n, int row, int k) const {
-    return *reinterpret_cast<const bf16x8*>(p + ((size_t)plane * n + row) * n + k);
+  __device__ __forceinline__ bf16x8 frag(int plane, int n, int rt, int kc, int lane) const {
+    return *reinterpret_cast<const bf16x8*>(p + ((((size_t)plane * (n / 16) + rt) * (n / 32) + kc) * 64 + lane) * 8);
   }
 };
 
@@ -73,97 +76,127 @@ __device__ __forceinline__ void cmma(const CFrag& a, const CFrag& b, bool conj_b
   ci = mma3(a.ih, a.il, b.rh, b.rl, ci);
 }
 
+// Row or column groups of 16 per workgroup: every table fragment a wave loads
+// serves kDftGroups groups (kDftGroups x 12 MFMAs per fragment load).
+constexpr int kDftGroups = 4;
+
 // Rows of every frame times F (or conj F): X[r][:] <- X[r][:] F, in place.
-// Block = 16 rows; wave w produces output columns [w N/4, (w+1) N/4).
+// Block = kDftGroups x 16 rows; wave w produces output columns [w N/4, (w+1) N/4)
+// of every row group.
 template <int N, bool INV>
 __global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows) {
   constexpr int TPW = N / 64;  // 16-column tiles per wave
-  const int r0 = blockIdx.x * 16;
+  constexpr int G = kDftGroups;
+  const int r0 = blockIdx.x * 16 * G;
   if (r0 >= rows) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, kq = lane >> 4;
-  floatx4 cr[TPW], ci[TPW];
+  floatx4 cr[G][TPW], ci[G][TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    cr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  }
-  const float2* xrow = X + (size_t)(r0 + lr) * N;
-  for (int kc = 0; kc < N; kc += 32) {
-    const int k0 = kc + kq * 8;
-    float re[8], im[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float2 v = xrow[k0 + i];
-      re[i] = v.x;
-      im[i] = v.y;
-    }
-    CFrag a;
-    split8(re, a.rh, a.rl);
-    split8(im, a.ih, a.il);
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int col = w * (N / 4) + t * 16 + lr;  // B[k][col] = F[col][k]
-      CFrag b{F.load(0, N, col, k0), F.load(1, N, col, k0), F.load(2, N, col, k0), F.load(3, N, col, k0)};
-      cmma(a, b, INV, cr[t], ci[t]);
+      cr[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ci[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int kc = 0; kc < N; kc += 32) {
+    const int k0 = kc + kq * 8;
+    CFrag a[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const float2* xrow = X + (size_t)(r0 + g * 16 + lr) * N;
+      float re[8], im[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float2 v = xrow[k0 + i];
+        re[i] = v.x;
+        im[i] = v.y;
+      }
+      split8(re, a[g].rh, a[g].rl);
+      split8(im, a[g].ih, a[g].il);
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      // B[k][col] = F[col][k], col = w N/4 + 16 t + lr
+      const int rt = w * (N / 64) + t, kb = kc / 32;
+      CFrag b{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
+              F.frag(3, N, rt, kb, lane)};
+#pragma unroll
+      for (int g = 0; g < G; ++g) cmma(a[g], b, INV, cr[g][t], ci[g][t]);
     }
   }
   __syncthreads();  // every wave has read the block's rows before any is overwritten
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int col = w * (N / 4) + t * 16 + lr;
+  for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) X[(size_t)(r0 + kq * 4 + i) * N + col] = make_float2(cr[t][i], ci[t][i]);
-  }
+    for (int t = 0; t < TPW; ++t) {
+      const int col = w * (N / 4) + t * 16 + lr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        X[(size_t)(r0 + g * 16 + kq * 4 + i) * N + col] = make_float2(cr[g][t][i], ci[g][t][i]);
+    }
 }
 
 // F (or conj F) times every column of each frame: X_f <- F X_f, in place.
-// Block = 16 columns of one frame (blockIdx.y); wave w produces rows [w N/4, (w+1) N/4).
+// Block = kDftGroups x 16 columns of one frame (blockIdx.y); wave w produces rows
+// [w N/4, (w+1) N/4) of every column group.
 template <int N, bool INV>
 __global__ __launch_bounds__(256) void k_dft_left(float2* __restrict__ X, DftPlanes F, int frames) {
   constexpr int TPW = N / 64;
+  constexpr int G = kDftGroups;
   const int f = blockIdx.y;
   if (f >= frames) return;
-  const int c0 = blockIdx.x * 16;
+  const int c0 = blockIdx.x * 16 * G;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lc = lane & 15, kq = lane >> 4;
   float2* fr = X + (size_t)f * N * N;
-  floatx4 cr[TPW], ci[TPW];
+  floatx4 cr[G][TPW], ci[G][TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    cr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  }
-  for (int kc = 0; kc < N; kc += 32) {
-    const int k0 = kc + kq * 8;
-    float re[8], im[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {  // B[k][col] = X[k][c0 + col]
-      const float2 v = fr[(size_t)(k0 + i) * N + c0 + lc];
-      re[i] = v.x;
-      im[i] = v.y;
-    }
-    CFrag b;
-    split8(re, b.rh, b.rl);
-    split8(im, b.ih, b.il);
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int row = w * (N / 4) + t * 16 + lc;  // A[row][k] = F[row][k]
-      CFrag a{F.load(0, N, row, k0), F.load(1, N, row, k0), F.load(2, N, row, k0), F.load(3, N, row, k0)};
+      cr[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ci[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int kc = 0; kc < N; kc += 32) {
+    const int k0 = kc + kq * 8;
+    CFrag b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      float re[8], im[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {  // B[k][col] = X[k][c0 + 16 g + col]
+        const float2 v = fr[(size_t)(k0 + i) * N + c0 + g * 16 + lc];
+        re[i] = v.x;
+        im[i] = v.y;
+      }
+      split8(re, b[g].rh, b[g].rl);
+      split8(im, b[g].ih, b[g].il);
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      // A[row][k] = F[row][k], row = w N/4 + 16 t + lc
+      const int rt = w * (N / 64) + t, kb = kc / 32;
+      CFrag a{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
+              F.frag(3, N, rt, kb, lane)};
       if (INV) {  // conj(F) X: negate the imaginary part of the table operand
         a.ih = neg8(a.ih);
         a.il = neg8(a.il);
       }
-      cmma(a, b, false, cr[t], ci[t]);
+#pragma unroll
+      for (int g = 0; g < G; ++g) cmma(a, b[g], false, cr[g][t], ci[g][t]);
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int row0 = w * (N / 4) + t * 16 + kq * 4;
+  for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) fr[(size_t)(row0 + i) * N + c0 + lc] = make_float2(cr[t][i], ci[t][i]);
-  }
+    for (int t = 0; t < TPW; ++t) {
+      const int row0 = w * (N / 4) + t * 16 + kq * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        fr[(size_t)(row0 + i) * N + c0 + g * 16 + lc] = make_float2(cr[g][t][i], ci[g][t][i]);
+    }
 }
 
 // Exit waves of the batch into the work frames: X[b][k] = o_b P_k.
@@ -316,14 +349,15 @@ int dft_err_slots(int n) { return (n / kDftTile) * (n / kDftTile); }
 
 template <int N>
 static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inverse, hipStream_t s) {
+  static_assert(N % (16 * kDftGroups) == 0, "whole row / column groups per block");
   DftPlanes F{planes};
   const int rows = frames * N;
   if (!inverse) {
-    pty_launch(k_dft_right<N, false>, dim3(rows / 16), dim3(256), 0, s, X, F, rows);
-    pty_launch(k_dft_left<N, false>, dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, false>, dim3(rows / (16 * kDftGroups)), dim3(256), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, false>, dim3(N / (16 * kDftGroups), frames), dim3(256), 0, s, X, F, frames);
   } else {
-    pty_launch(k_dft_left<N, true>, dim3(N / 16, frames), dim3(256), 0, s, X, F, frames);
-    pty_launch(k_dft_right<N, true>, dim3(rows / 16), dim3(256), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, true>, dim3(N / (16 * kDftGroups), frames), dim3(256), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, true>, dim3(rows / (16 * kDftGroups)), dim3(256), 0, s, X, F, rows);
   }
   return hipGetLastError();
 }

@@ -404,8 +404,14 @@ float bf16_val(uint16_t h) {
   return f;
 }
 
-// Host-built split planes [4][n][n] (re_hi, re_lo, im_hi, im_lo) of
-// F[u][x] = exp(-2 pi i u x / n) / sqrt(n), evaluated in double.
+// Host-built split planes (re_hi, re_lo, im_hi, im_lo) of
+// F[u][x] = exp(-2 pi i u x / n) / sqrt(n), evaluated in double, each stored in
+// MFMA fragment order: [u / 16][x / 32][lane = 16 ((x % 32) / 8) + u % 16][x % 8],
+// so that the 16 x 32 fragment a wave needs is one contiguous 1 KB read.
+static size_t dft_frag_index(int n, int plane, int u, int x) {
+  const int lane = 16 * ((x % 32) / 8) + u % 16;
+  return ((((size_t)plane * (n / 16) + u / 16) * (n / 32) + x / 32) * 64 + lane) * 8 + x % 8;
+}
 std::vector<uint16_t> dft_planes(int n) {
   std::vector<uint16_t> pl((size_t)4 * n * n);
   const double pi = 3.14159265358979323846, sc = 1.0 / std::sqrt((double)n);
@@ -416,8 +422,8 @@ std::vector<uint16_t> dft_planes(int n) {
       for (int c = 0; c < 2; ++c) {
         const uint16_t hi = bf16_rne((float)v[c]);
         const uint16_t lo = bf16_rne((float)(v[c] - (double)bf16_val(hi)));
-        pl[((size_t)(2 * c) * n + u) * n + x] = hi;
-        pl[((size_t)(2 * c + 1) * n + u) * n + x] = lo;
+        pl[dft_frag_index(n, 2 * c, u, x)] = hi;
+        pl[dft_frag_index(n, 2 * c + 1, u, x)] = lo;
       }
     }
   return pl;
