@@ -196,6 +196,15 @@ def near_field_leg(steps=5):
             "variant": variant, "steps": steps, "generation_s": round(gen, 1), "final_data_error": err}
 
 
+# The paper's own QPT scans (Table 1: 100 points, 1024^2 patterns, 0.02 mm steps over 2.71 um
+# (far) or 6.5 um (near) object pixels; near field 19.9 mm at 514.5 nm with 6.5 um pixels, so
+# F_px = 6.5^2 / (0.5145 * 19900)) and their per-iteration pc-ePIE times on a TITAN Xp (captions of
+# Figs. 4 and 3).
+PAPER_FRAME = 1024
+PAPER_SCAN_SIDE = 10
+PAPER_SHAPES = (("far", 0, 7, 0.0, 452.2), ("near", 1, 3, 4.13e-3, 640.0))  # name, geometry, step, F_px, ms
+
+
 def paper_shapes_leg(steps=5):
     """The paper's scans (100 patterns of 1024^2, one mode): far field at a 7 px step, near field at
     3 px with F_px = 4.13e-3; sequential updates (batch 1, as the paper's loop) and batch 10."""
@@ -203,14 +212,14 @@ def paper_shapes_leg(steps=5):
     import datagen
     import paper_2406_06640_amd as P
     out = {}
-    for name, geometry, step, paper_ms in (("far", 0, 7, 452.2), ("near", 1, 3, 640.0)):
-        n = 1024
-        extent = 9 * step + n + 2
+    for name, geometry, step, fresnel_px, paper_ms in PAPER_SHAPES:
+        n = PAPER_FRAME
+        extent = (PAPER_SCAN_SIDE - 1) * step + n + 2
         side = int(np.ceil(extent / 16.0) * 16)
         spec = dict(datagen.CONFIGS["far64"])
-        spec.update(geometry=geometry, obj=(side, side), n=n, n_side=10, step=step, jitter=1, k=1,
+        spec.update(geometry=geometry, obj=(side, side), n=n, n_side=PAPER_SCAN_SIDE, step=step, jitter=1, k=1,
                     powers=(1.0,), radius=n // 4, defocus=1.0 if geometry == 0 else 0.0, sigma_data=1.0,
-                    counts=1e6, fresnel_px=4.13e-3 if geometry == 1 else 0.0, sigma=1.0, batch=1)
+                    counts=1e6, fresnel_px=fresnel_px, sigma=1.0, batch=1)
         t0 = time.time()
         s = datagen.make_scan(spec, [1006, geometry])
         gen = time.time() - t0
