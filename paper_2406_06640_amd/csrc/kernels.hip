@@ -1,20 +1,23 @@
 // HIP kernels (gfx950) of one pc-ePIE batch update and its per-iteration bookkeeping.
 //
 // One batch of B scan positions, each with K incoherent probe modes, moves
-// through these passes (frames live in X[b][k][N][N], complex64):
-//   fwd_rows   psi = o_b P_k (box gather fused), 1D transform along x       (Eq. 1)
-//   fwd_cols   1D transform along y; I_mod = sum_k |Psi_k|^2 (mode sum); vertical
-//              half of the Gaussian blur of sqrt(I_mod) (or I_mod)          (Eq. 6-7, box 1)
-//   inv_cols   horizontal half of the blur, modulus factor, data error;
-//              Psi' = factor Psi, inverse 1D transform along y
-//   inv_rows   inverse along x -> psi'; dpsi = psi' - o_b P_k; per-slot object
-//              numerator sum_k conj(P_k) dpsi_k; X <- conj(o_b) dpsi_k
-//   (fwd_rows side blocks: per-tile max of W = sum_b |P(r - r_b)|^2 and
-//              V = sum_b |o_b|^2, both from the pre-update state)
-//   obj_update N_O gathered per object tile in slot order; O update (and, in
-//              constraint windows, the C-bar sums of Eq. 11)
-//   post       N_P,k = sum_b X[b][k] in slot order, P_k update, sum_k |P_k|^2;
-//              complex constraint, Eq. (9)-(10) (box 2)
+// through seven launches (frames live in X[b][k][N][N], complex64):
+//   fwd_rows        psi = o_b P_k (box gather fused), 1D transform along x      (Eq. 1);
+//                   side blocks: per-tile max of W = sum_b |P(r - r_b)|^2 and
+//                   V = sum_b |o_b|^2, both from the pre-update state
+//   fwd_cols        1D transform along y; I_mod = sum_k |Psi_k|^2 (mode sum); vertical
+//                   half of the Gaussian blur of sqrt(I_mod) (or I_mod)        (Eq. 6-7, box 1)
+//   modulus_factor  horizontal half of the blur over whole rows, modulus factor, data error
+//   inv_cols        Psi_k again (recomputed in the far field), Psi' = factor Psi,
+//                   inverse 1D transform along y
+//   inv_rows        inverse along x -> psi'; dpsi = psi' - o_b P_k; per-slot object
+//                   numerator sum_k conj(P_k) dpsi_k; X <- conj(o_b) dpsi_k
+//   obj_update      probe blocks: N_P,k = sum_b X[b][k], P_k update, sum_k |P_k|^2 into
+//                   the probe-power copy the next batch reads; tile blocks: N_O gathered
+//                   per object tile in slot order, O update and, in constraint windows,
+//                   the C-bar sums of Eq. (11)
+//   constraint      the complex constraint, Eq. (9)-(10)                      (box 2)
+// The launch variant cols_fused does fwd_cols, modulus_factor and inv_cols in one launch.
 // Near-field frames use the separable paraxial transfer function: each 1D
 // pass is forward FFT, multiply by h, inverse FFT.  Every reduction runs in a
 // fixed order (no atomics), so results are bitwise reproducible.
