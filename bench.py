@@ -88,6 +88,16 @@ def per_slot_bytes(name, n, k):
     }.get(name)
 
 
+def iteration_hbm(n, k, n_pos, ms_per_step):
+    """Algorithmic HBM bytes of a whole far-field iteration (every batch pass, per-slot figures of
+    per_slot_bytes x positions) against the measured step time: the average rate over all kernels."""
+    classes = ("fwd_rows", "fwd_cols", "modulus_factor", "inv_cols", "inv_rows_update", "obj_probe_update")
+    total = sum(per_slot_bytes(c, n, k) for c in classes) * n_pos
+    gbs = total / (ms_per_step * 1e-3) / 1e9
+    return {"algorithmic_bytes": int(total), "achieved": round(gbs, 1), "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def build_workload(n_pos=None):
     import datagen
     spec = datagen.CONFIGS["far256_k4"]
@@ -454,6 +464,7 @@ def main():
                    "positions": n_pos, "modes": k, "frame": n, "batch": args.batch,
                    "column_tile_variant": col_variant},
         "roofline": roof,
+        "iteration_hbm": iteration_hbm(n, k, n_pos, ms_per_step),
         "kernel_ms_per_step": {nm: round(ms, 4) for nm, (ms, c) in prof.items() if c},
         "final_data_error": float(errs[-1]),
     }
