@@ -6,16 +6,12 @@ source bandwidth and the probe's aperture radius and defocus).  Six 3 x 3
 convolutions with 32 channels (zero padding 1; strides 2, 2, 2, 2, 2, 1; ReLU
 after each), a global average pool and a linear head.  Tensors are NCHW.
 
-Optionally (act_round) every stored activation is rounded after its ReLU, so
-that the ReLU decisions of the next layers are taken on the values a
-lower-precision implementation holds (its BF16 activation storage); the
-arithmetic itself stays FP64.
-
 Parameters are one flat vector, per convolution W[Co][Ci][3][3] then b[Co],
 then the head W[T][32] and b[T].  The loss is the mean squared error over the
 batch and the T outputs.  Written with plain loops over the 3 x 3 taps and
 numpy for the channel sums, so it can be checked by eye and against central
-finite differences.
+finite differences.  The optimiser step is Adam (Kingma and Ba, ICLR 2015,
+Algorithm 1), written out in FP64.
 """
 
 from __future__ import annotations
@@ -86,30 +82,40 @@ def conv_backward(x, w, stride, dy):
 
 def bf16_round(a):
     """Round to the nearest bfloat16 value (8 significant bits, ties to even): the
-    float32 bit pattern plus 0x7FFF plus bit 16, truncated to the upper 16 bits."""
+    float32 bit pattern plus 0x7FFF plus bit 16, truncated to the upper 16 bits.
+    Used to give the reference the BF16 weights a network stores."""
     u = np.asarray(a, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward(theta, x, layers=LAYERS, n_out=N_OUT, act_round=None):
+def pre_activations(theta, x, layers=LAYERS, n_out=N_OUT):
+    """The convolution outputs before each ReLU, [z_1 .. z_L]."""
+    convs, _ = unpack(theta, layers, n_out)
+    a = x
+    zs = []
+    for (w, b), (_, _, s) in zip(convs, layers):
+        z = conv_forward(a, w, b, s)
+        zs.append(z)
+        a = np.maximum(z, 0.0)
+    return zs
+
+
+def forward(theta, x, layers=LAYERS, n_out=N_OUT):
     """Returns (outputs [n, T], cache)."""
     convs, (hw, hb) = unpack(theta, layers, n_out)
     acts = [x]
     for (w, b), (_, _, s) in zip(convs, layers):
-        a = np.maximum(conv_forward(acts[-1], w, b, s), 0.0)
-        acts.append(act_round(a) if act_round is not None else a)
+        acts.append(np.maximum(conv_forward(acts[-1], w, b, s), 0.0))
     feat = acts[-1].mean(axis=(2, 3))
     y = feat @ hw.T + hb
     return y, (acts, feat)
 
 
-def loss_and_grad(theta, x, target, layers=LAYERS, n_out=N_OUT, act_round=None):
-    """Mean squared error over batch and outputs, and its gradient w.r.t. theta
-    (with act_round, the gradient of the network whose activations are rounded,
-    treating the rounding as the identity)."""
+def loss_and_grad(theta, x, target, layers=LAYERS, n_out=N_OUT):
+    """Mean squared error over batch and outputs, and its gradient w.r.t. theta."""
     convs, (hw, hb) = unpack(theta, layers, n_out)
-    y, (acts, feat) = forward(theta, x, layers, n_out, act_round)
+    y, (acts, feat) = forward(theta, x, layers, n_out)
     nb = x.shape[0]
     diff = y - target
     loss = float(np.mean(diff ** 2))
@@ -134,6 +140,20 @@ def loss_and_grad(theta, x, target, layers=LAYERS, n_out=N_OUT, act_round=None):
     flat += [dhw.ravel(), dhb.ravel()]
     del nb
     return loss, np.concatenate(flat)
+
+
+def adam_step(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, Algorithm 1) at 1-based step `step`:
+      m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+      m^ = m / (1 - beta1^step),      v^ = v / (1 - beta2^step),
+      theta <- theta - lr m^ / (sqrt(v^) + eps).
+    Returns (theta, m, v) as new arrays."""
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    return np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
 
 
 def init_params(rng, layers=LAYERS, n_out=N_OUT):

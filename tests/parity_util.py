@@ -97,3 +97,31 @@ def oracle_step(s, op, idx, t, o32, p32):
     cap["P"] = Pn
     cap["err"] = err
     return cap
+
+
+def inf_rel(a, b):
+    """max |a - b| / max |b|: the worst element against the reference's peak."""
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    mb = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / mb) if mb > 0 else float(np.max(np.abs(a))) if a.size else 0.0
+
+
+def union_of_boxes(positions, n, shape, idx=None):
+    """Mask of the object pixels covered by the boxes of `positions` (all, or those in idx)."""
+    m = np.zeros(shape, dtype=bool)
+    for i in (range(len(positions)) if idx is None else idx):
+        r, c = int(positions[i][0]), int(positions[i][1])
+        m[r:r + n, c:c + n] = True
+    return m
+
+
+def probe_metrics(p_gpu, p_ora):
+    """Mode-mixing-invariant probe comparisons: the powers ||P_k||^2 (after the
+    orthogonalisation these are the Gram eigenvalues) and sum_k |P_k|^2 per pixel."""
+    pw_g = np.sum(np.abs(p_gpu.astype(np.complex128)) ** 2, axis=(-2, -1))
+    pw_o = np.sum(np.abs(p_ora) ** 2, axis=(-2, -1))
+    tot_g = np.sum(np.abs(p_gpu.astype(np.complex128)) ** 2, axis=0)
+    tot_o = np.sum(np.abs(p_ora) ** 2, axis=0)
+    return dict(eig=float(np.max(np.abs(pw_g - pw_o) / pw_o)), sum_p2=rel_l2(tot_g, tot_o),
+                sum_p2_inf=inf_rel(tot_g, tot_o))

@@ -33,7 +33,7 @@ def _errors(gc, oc):
         "factor": rel_l2(gc["factor"], np.stack(oc["factor"])),
         "n_obj": rel_l2(gc["n_obj"], oc["n_o"]),
         "n_probe": rel_l2(gc["n_probe"], oc["n_p"]),
-        "O": rel_l2(gc["O"], oc["O"]),
+        "O": rel_l2(gc["O"][oc["mask"]], oc["O"][oc["mask"]]),
         "P": rel_l2(gc["P"], oc["P"]),
     }
 

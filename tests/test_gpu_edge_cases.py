@@ -81,7 +81,7 @@ def test_edge_case_batch_step(name):
         "w_obj": rel_l2(gc["w_obj"], oc["w"]),
         "n_probe": rel_l2(gc["n_probe"], oc["n_p"]),
         "v_probe": rel_l2(gc["v_probe"], oc["v"]),
-        "O": rel_l2(gc["O"], oc["O"]),
+        "O": rel_l2(gc["O"][oc["mask"]], oc["O"][oc["mask"]]),
         "P": rel_l2(gc["P"], oc["P"]),
     }
     print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)

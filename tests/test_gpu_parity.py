@@ -13,12 +13,16 @@ import numpy as np
 import pytest
 
 import oracle as ora
-from parity_util import gpu_step, make_case, oracle_step, params_pair, rel_l2, state32
+from parity_util import gpu_step, inf_rel, make_case, oracle_step, params_pair, rel_l2, state32
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 TOL_FACTOR = 1e-4
+# worst single element against the reference's peak magnitude: FP32 rounding of one
+# element through ~20 transform stages is ~1e-6 of the peak; dim pixels of psi' carry
+# the modulus factor's relative error, so the bar is set an order above that
+TOL_INF = 1e-4
 
 
 def _announce(msg):
@@ -32,15 +36,25 @@ def _compare_step(gc, oc, cp, check_probe=True, tol=TOL):
     out["factor"] = rel_l2(gc["factor"], np.stack(oc["factor"]))
     out["n_obj"] = rel_l2(gc["n_obj"], oc["n_o"])
     out["w_obj"] = rel_l2(gc["w_obj"], oc["w"])
-    out["O"] = rel_l2(gc["O"], oc["O"])
+    m = oc["mask"]  # union of the batch's boxes: the only pixels the step changes
+    out["O"] = rel_l2(gc["O"][m], oc["O"][m])
     out["P"] = rel_l2(gc["P"], oc["P"])
     if check_probe:
         out["n_probe"] = rel_l2(gc["n_probe"], oc["n_p"])
         out["v_probe"] = rel_l2(gc["v_probe"], oc["v"])
-    print({k: f"{v:.2e}" for k, v in out.items()}, flush=True)
+    inf = {"psi_new": inf_rel(gc["psi_new"], np.stack(oc["psi_new"])), "n_obj": inf_rel(gc["n_obj"], oc["n_o"]),
+           "O": inf_rel(gc["O"][m], oc["O"][m]), "P": inf_rel(gc["P"], oc["P"])}
+    if check_probe:
+        inf["n_probe"] = inf_rel(gc["n_probe"], oc["n_p"])
+    print({k: f"{v:.2e}" for k, v in out.items()}, "worst element:", {k: f"{v:.1e}" for k, v in inf.items()},
+          flush=True)
     for k, v in out.items():
         lim = TOL_FACTOR if k == "factor" else tol
         assert v <= lim, f"{k}: relative L2 {v:.3e} > {lim:g}"
+    for k, v in inf.items():
+        assert v <= max(TOL_INF, 10 * tol), f"{k}: worst element {v:.3e} of the peak > {TOL_INF:g}"
+    # pixels outside the batch's boxes keep their values exactly
+    np.testing.assert_array_equal(gc["O"][~m], oc["O"][~m].astype(np.complex64))
     return out
 
 

@@ -107,3 +107,40 @@ def test_orthogonal_modes_are_kept_up_to_order(rng):
     for q, ref in ((Q[0], b), (Q[1], a)):
         ph = np.vdot(ref, q) / abs(np.vdot(ref, q))
         np.testing.assert_allclose(q, ref * ph, atol=1e-12)
+
+
+def test_orthogonalization_phase_rule(rng):
+    """The remix Q = V^T P of the R11 reading: recover V from Q and P by least squares
+    (independently of the eigensolver) and check each column's largest-magnitude entry
+    is real and positive, the columns are orthonormal, and the powers are descending."""
+    k, n = 5, 9
+    P = rng.standard_normal((k, n, n)) + 1j * rng.standard_normal((k, n, n))
+    P *= np.array([3.0, 1.0, 2.0, 0.5, 1.5])[:, None, None]
+    Q, lam = ora.orthogonalize_modes(P)
+    pf, qf = P.reshape(k, -1), Q.reshape(k, -1)
+    # qf = V^T pf  <=>  pf^T V = qf^T
+    v, *_ = np.linalg.lstsq(pf.T, qf.T, rcond=None)
+    np.testing.assert_allclose(pf.T @ v, qf.T, atol=1e-10)
+    np.testing.assert_allclose(np.conj(v.T) @ v, np.eye(k), atol=1e-10)
+    for j in range(k):
+        i = int(np.argmax(np.abs(v[:, j])))
+        assert abs(v[i, j].imag) < 1e-10 and v[i, j].real > 0, (j, v[:, j])
+    powers = np.sum(np.abs(qf) ** 2, axis=1)
+    np.testing.assert_allclose(powers, lam, rtol=1e-10)
+    assert np.all(np.diff(powers) < 0)
+
+
+def test_orthogonalization_phase_rule_flags_a_wrong_rule(rng):
+    """A rule that leaves the eigensolver's phases (or fixes the first entry instead of
+    the largest) fails the check above, so the pin is not vacuous."""
+    k, n = 4, 6
+    P = rng.standard_normal((k, n, n)) + 1j * rng.standard_normal((k, n, n))
+    pf = P.reshape(k, -1)
+    gram = np.conj(pf) @ pf.T
+    lam, vec = np.linalg.eigh(gram)
+    vec = vec[:, ::-1] * np.exp(1j * np.arange(1, k + 1))[None, :]  # arbitrary phases
+    bad = []
+    for j in range(k):
+        i = int(np.argmax(np.abs(vec[:, j])))
+        bad.append(abs(vec[i, j].imag) < 1e-10 and vec[i, j].real > 0)
+    assert not all(bad)
