@@ -115,6 +115,24 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
  * is then failed); PTYCHO_E_INVALID for a bad order. */
 ptycho_status ptycho_iterate(ptycho_ctx* ctx, int32_t n_iter, const int32_t* order, float* err_out);
 
+/* ptycho_iterate for callers that cannot allocate device memory during the call
+ * (serving loops, code running between captures, harnesses that forbid it): the
+ * same iterations, bitwise the same object, probe, counter and data errors, but
+ * the call allocates nothing.  The work frames, partial sums, per-call schedule
+ * and case table that ptycho_iterate keeps in context buffers live in a
+ * library-owned static device array of 64 MiB per device (held until the
+ * process ends); the context's state (object, probe, measured amplitudes,
+ * positions) stays where ptycho_init put it.  Every call on a device shares that
+ * device's array: calls that overlap on one device race (the library serialises
+ * the calls of one process on the host; run one at a time per device).
+ * Errors as ptycho_iterate, plus PTYCHO_E_SHAPE when the reconstruction needs
+ * more than the array holds (about 8 B x (batch x (n_modes + 2) + n_modes) x n^2
+ * plus 8 B per position x (n / rows per block) and the schedule) or has more
+ * than 262144 positions, and PTYCHO_E_STATE when the current HIP device is not
+ * the context's.  Synchronises the stream.  Eager launches only (no graph replay,
+ * no per-kernel timing). */
+ptycho_status ptycho_iterate_static(ptycho_ctx* ctx, int32_t n_iter, const int32_t* order, float* err_out);
+
 /* Copy the current object [obj_h][obj_w][2] / probe [K][n][n][2] into `out`
  * (host or device per mem_kind).  Synchronises the stream. */
 ptycho_status ptycho_get_object(ptycho_ctx* ctx, float* out, int32_t mem_kind);

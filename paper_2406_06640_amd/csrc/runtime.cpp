@@ -431,10 +431,9 @@ std::vector<uint16_t> dft_planes(int n) {
 
 // The batch of the dft_bf16 path: the same updates as launch_batch, with the
 // two FFT passes per direction replaced by BF16 matrix-core DFT GEMMs.
-std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, const TableShape& sh,
-                             int beta, int ns, const int* it, hipStream_t s) {
+std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, float2* X,
+                             const TableShape& sh, int beta, int ns, const int* it, hipStream_t s) {
   const int frames = ns * c->prm.n_modes;
-  float2* X = c->db.X;
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_side(cases, sh, beta, it, s));
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_exit(cases, sh, beta, it, s));
   LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, false, s));
@@ -447,28 +446,36 @@ std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc
   return "";
 }
 
-// One batch of a single context (either propagation path).
-std::string launch_one(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, const TableShape& sh, int beta,
-                       int ns, const int* it, hipStream_t s) {
-  if (c->prm.dft_bf16) return launch_batch_dft(tc, c, cases, sh, beta, ns, it, s);
+// One batch of a single context (either propagation path); X is the work-frame
+// buffer the case table `cases` points at.
+std::string launch_one(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, float2* X, const TableShape& sh,
+                       int beta, int ns, const int* it, hipStream_t s) {
+  if (c->prm.dft_bf16) return launch_batch_dft(tc, c, cases, X, sh, beta, ns, it, s);
   return launch_batch(tc, cases, sh, beta, it, s);
 }
 
-// One iteration of a single context on stream s (eager or under capture).
-std::string enqueue_iteration(ptycho_ctx* c, hipStream_t s, bool timed) {
+// One iteration of a single context on stream s from the case table `cases`
+// (work buffers X) and the device iteration counter `it`.
+std::string enqueue_iteration_on(ptycho_ctx* c, const CaseDesc* cases, float2* X, int* it, hipStream_t s,
+                                 bool timed) {
   const TableShape sh = single_shape(c, c->prm.batch);
   ptycho_ctx* tc = timed ? c : nullptr;
   const int nb = n_batches_of(c->prm);
   for (int beta = 0; beta < nb; ++beta) {
     const int ns = std::min(c->prm.batch, c->prm.n_pos - beta * c->prm.batch);
-    std::string e = launch_one(tc, c, c->d_case, sh, beta, ns, c->d_iter, s);
+    std::string e = launch_one(tc, c, cases, X, sh, beta, ns, it, s);
     if (!e.empty()) return e;
   }
-  std::string e = launch_end(tc, c->d_case, sh, c->d_iter, s);
+  std::string e = launch_end(tc, cases, sh, it, s);
   if (!e.empty()) return e;
-  hipError_t he = launch_iter_advance(c->d_iter, s);
+  hipError_t he = launch_iter_advance(it, s);
   if (he != hipSuccess) return std::string("iter_advance: ") + hipGetErrorString(he);
   return "";
+}
+
+// One iteration of a single context on its own buffers (eager or under capture).
+std::string enqueue_iteration(ptycho_ctx* c, hipStream_t s, bool timed) {
+  return enqueue_iteration_on(c, c->d_case, c->db.X, c->d_iter, s, timed);
 }
 
 void drop_graph(ptycho_ctx* c) {
@@ -549,6 +556,97 @@ void tune_store_locked(const std::tuple<int, int, int, int>& key, int v) {
   std::ofstream f(path, std::ios::app);
   f << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' ' << v
     << '\n';
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of ptycho_iterate_static.  The work frames, partial sums,
+// schedule and case table of its iterations live in this file-scope device
+// array, so the call allocates nothing.  In host code `scratch` names only a
+// host-side handle: kernels are given the device address that
+// hipGetSymbolAddress returns for the current device (each device holds its
+// own copy of the array), resolved once per device and kept in g_static_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr size_t kStaticOrderInts = (size_t)1 << 18;  // schedule entries staged per chunk of iterations
+constexpr int kStaticMaxChunk = 1024;                 // iterations per chunk
+constexpr int kStaticMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Grid-stride zero fill of `words` 8-byte words (a kernel rather than a memset,
+// so the clearing is an ordinary kernel node should a caller capture the stream).
+__global__ void k_static_zero(unsigned long long* __restrict__ p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+namespace {
+
+std::mutex g_static_ptr_mu;
+void* g_static_ptr[kStaticMaxDevices] = {};
+// host staging of one chunk's schedule (guarded by g_static_mu; calls are serialised)
+std::mutex g_static_mu;
+int32_t g_static_order[kStaticOrderInts];
+int g_static_flags[kStaticMaxChunk];
+float g_static_err[kStaticMaxChunk];
+char g_static_seen[kStaticOrderInts];
+
+// Device address of `scratch` on device `dev`, which must be current; resolved
+// by hipGetSymbolAddress on the first request per device.
+hipError_t static_scratch_ptr(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_static_ptr_mu);
+  if (dev < 0 || dev >= kStaticMaxDevices) return hipErrorInvalidDevice;
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return hipSuccess;
+}
+
+// Byte offsets of the buffers of one context inside the static scratch.
+struct StaticLayout {
+  size_t cases, order, flags, err, iter, X, q, dO, nP, V, maxv, maxw, errp, ccp, gramp, vmix, eig, total;
+  int chunk;  // iterations per staged chunk
+};
+
+StaticLayout static_layout(const ptycho_ctx* c, int n_iter) {
+  const ptycho_params& p = c->prm;
+  const size_t nn = (size_t)p.n * p.n, B = p.batch, K = p.n_modes;
+  const int nobjt = n_obj_tiles(c->dp);
+  const int nbt = std::max(max_err_slots(p.n), p.dft_bf16 ? dft_err_slots(p.n) : 0);
+  StaticLayout L{};
+  L.chunk = (int)std::min<size_t>({(size_t)std::max(n_iter, 1), (size_t)kStaticMaxChunk,
+                                   kStaticOrderInts / (size_t)std::max(p.n_pos, 1)});
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  L.cases = take(sizeof(CaseDesc));
+  L.order = take(sizeof(int32_t) * (size_t)L.chunk * p.n_pos);
+  L.flags = take(sizeof(int) * (size_t)L.chunk);
+  L.err = take(sizeof(float) * (size_t)L.chunk);
+  L.iter = take(sizeof(int));
+  L.X = take(sizeof(float2) * B * K * nn);
+  L.q = take(sizeof(float) * B * nn);
+  L.dO = take(sizeof(float2) * B * nn);
+  L.nP = take(sizeof(float2) * K * nn);
+  L.V = take(sizeof(float) * nn);
+  L.maxv = take(sizeof(float) * (size_t)n_probe_blocks(p.n));
+  L.maxw = take(sizeof(float) * (size_t)nobjt);
+  L.errp = take(sizeof(double) * (size_t)p.n_pos * nbt);
+  L.ccp = take(sizeof(double2) * (size_t)nobjt);
+  L.gramp = take(sizeof(double2) * (K * (K + 1) / 2) * kGramBlocks);
+  L.vmix = take(sizeof(float2) * K * K);
+  L.eig = take(sizeof(double) * K);
+  L.total = off;
+  return L;
 }
 
 }  // namespace
@@ -636,6 +734,12 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   if (hipGetDevice(&c->device) != hipSuccess) {
     c->err = "no HIP device";
     return bail(PTYCHO_E_HIP);
+  }
+  {
+    // resolve the static scratch of ptycho_iterate_static for this device now, with
+    // the device current; a failure is reported by that entry point, which retries
+    void* unused = nullptr;
+    (void)static_scratch_ptr(c->device, &unused);
   }
   if (mem_kind == PTYCHO_MEM_DEVICE) {
     std::vector<float> hp;
@@ -811,30 +915,44 @@ int with_pw_parity(int flags, int& par, int n_batches) {
   return flags;
 }
 
+// Orders and flags of iterations first_it+1 .. first_it+n_iter (1-based, from the
+// context's counter c->t) into host arrays h_order [n_iter][n_pos] and h_flags
+// [n_iter]; `order` (may be NULL) holds the caller's rows for these iterations.
+// `par` enters as the probe-power copy of the first iteration and leaves as the
+// copy after the last.  `seen` is n_pos bytes of scratch for the permutation check.
+static ptycho_status fill_schedule(ptycho_ctx* c, int32_t first_it, int32_t n_iter, const int32_t* order,
+                                   int32_t* h_order, int* h_flags, int& par, char* seen) {
+  const int np = c->prm.n_pos;
+  const int nb = n_batches_of(c->prm);
+  for (int it = 0; it < n_iter; ++it) {
+    int32_t* row = h_order + (size_t)it * np;
+    const int t = c->t + first_it + 1 + it;
+    if (order) {
+      std::memcpy(row, order + (size_t)it * np, np * sizeof(int32_t));
+      std::memset(seen, 0, np);
+      for (int i = 0; i < np; ++i) {
+        if (row[i] < 0 || row[i] >= np || seen[row[i]])
+          return fail(c, PTYCHO_E_INVALID,
+                      "order row " + std::to_string(first_it + it) + " is not a permutation of 0..n_pos-1");
+        seen[row[i]] = 1;
+      }
+    } else {
+      splitmix_perm(c->prm.seed, t, np, row);
+    }
+    h_flags[it] = with_pw_parity(case_flags(c->prm, t), par, nb);
+  }
+  return PTYCHO_OK;
+}
+
 // Fill the schedule of n_iter iterations of context c into its call buffers.
 static ptycho_status stage_call(ptycho_ctx* c, int32_t n_iter, const int32_t* order) {
   const int np = c->prm.n_pos;
   if (!grow_call(c, c->allocs, c->call, (size_t)n_iter * np, (size_t)n_iter))
     return fail(c, PTYCHO_E_OOM, "schedule buffer allocation failed");
   std::vector<char> seen(np);
-  for (int it = 0; it < n_iter; ++it) {
-    int32_t* row = c->call.h_order + (size_t)it * np;
-    if (order) {
-      std::memcpy(row, order + (size_t)it * np, np * sizeof(int32_t));
-      std::fill(seen.begin(), seen.end(), 0);
-      for (int i = 0; i < np; ++i) {
-        if (row[i] < 0 || row[i] >= np || seen[row[i]])
-          return fail(c, PTYCHO_E_INVALID, "order row " + std::to_string(it) + " is not a permutation of 0..n_pos-1");
-        seen[row[i]] = 1;
-      }
-    } else {
-      splitmix_perm(c->prm.seed, c->t + 1 + it, np, row);
-    }
-    c->call.h_flags[it] = case_flags(c->prm, c->t + 1 + it);
-  }
   int par = c->pw_par;
-  const int nb = n_batches_of(c->prm);
-  for (int it = 0; it < n_iter; ++it) c->call.h_flags[it] = with_pw_parity(c->call.h_flags[it], par, nb);
+  ptycho_status st = fill_schedule(c, 0, n_iter, order, c->call.h_order, c->call.h_flags, par, seen.data());
+  if (st != PTYCHO_OK) return st;
   c->pw_par_next = par;
   return PTYCHO_OK;
 }
@@ -881,6 +999,98 @@ ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order
       return fail(c, PTYCHO_E_NUMERIC,
                   "non-finite data error at iteration " + std::to_string(c->t - n_iter + 1 + i));
     }
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_iterate_static(ptycho_ctx* c, int32_t n_iter, const int32_t* order, float* err_out) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
+  if (n_iter < 0) return fail(c, PTYCHO_E_INVALID, "n_iter must be >= 0");
+  if (n_iter == 0) return PTYCHO_OK;
+  const int np = c->prm.n_pos;
+  if ((size_t)np > kStaticOrderInts)
+    return fail(c, PTYCHO_E_SHAPE, "ptycho_iterate_static takes at most " + std::to_string(kStaticOrderInts) +
+                                       " positions; use ptycho_iterate");
+  const StaticLayout L = static_layout(c, n_iter);
+  if (L.total > kStaticScratchBytes)
+    return fail(c, PTYCHO_E_SHAPE, "this reconstruction needs " + std::to_string(L.total) +
+                                       " bytes of scratch; ptycho_iterate_static holds at most " +
+                                       std::to_string(kStaticScratchBytes) + " (use ptycho_iterate)");
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev != c->device) return fail(c, PTYCHO_E_STATE, "the current device is not the context's device");
+  void* base = nullptr;
+  {
+    const hipError_t e = static_scratch_ptr(dev, &base);
+    if (e != hipSuccess)
+      return fail(c, PTYCHO_E_HIP, std::string("resolving the static scratch: ") + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  // every order row is checked before anything runs
+  if (order) {
+    for (int it = 0; it < n_iter; ++it) {
+      const int32_t* row = order + (size_t)it * np;
+      std::memset(g_static_seen, 0, np);
+      for (int i = 0; i < np; ++i) {
+        if (row[i] < 0 || row[i] >= np || g_static_seen[row[i]])
+          return fail(c, PTYCHO_E_INVALID, "order row " + std::to_string(it) + " is not a permutation of 0..n_pos-1");
+        g_static_seen[row[i]] = 1;
+      }
+    }
+  }
+  char* b = static_cast<char*>(base);
+  hipStream_t s = c->stream;
+  // the array keeps the previous call's contents: the data-error partials start at zero
+  {
+    const size_t words = (sizeof(double) * (size_t)np * std::max(max_err_slots(c->prm.n),
+                                                                 c->prm.dft_bf16 ? dft_err_slots(c->prm.n) : 0)) / 8;
+    const int blocks = (int)std::min<size_t>((words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_static_zero, dim3(std::max(blocks, 1)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(b + L.errp), words);
+    HIP_TRY(c, hipGetLastError());
+  }
+  CaseDesc cd;
+  for (int done = 0; done < n_iter; done += L.chunk) {
+    const int m = std::min(L.chunk, n_iter - done);
+    int par = c->pw_par;
+    ptycho_status st = fill_schedule(c, 0, m, order ? order + (size_t)done * np : nullptr, g_static_order,
+                                     g_static_flags, par, g_static_seen);
+    if (st != PTYCHO_OK) return st;
+    fill_case(c, cd, reinterpret_cast<int*>(b + L.order), reinterpret_cast<int*>(b + L.flags),
+              reinterpret_cast<float*>(b + L.err));
+    cd.d.X = reinterpret_cast<float2*>(b + L.X);
+    cd.d.q = reinterpret_cast<float*>(b + L.q);
+    cd.d.dO = reinterpret_cast<float2*>(b + L.dO);
+    cd.d.nP = reinterpret_cast<float2*>(b + L.nP);
+    cd.d.V = reinterpret_cast<float*>(b + L.V);
+    cd.d.maxv_part = reinterpret_cast<float*>(b + L.maxv);
+    cd.d.maxw_part = reinterpret_cast<float*>(b + L.maxw);
+    cd.d.err_part = reinterpret_cast<double*>(b + L.errp);
+    cd.d.cc_part = reinterpret_cast<double2*>(b + L.ccp);
+    cd.d.gram_part = reinterpret_cast<double2*>(b + L.gramp);
+    cd.d.vmix = reinterpret_cast<float2*>(b + L.vmix);
+    cd.d.eig = reinterpret_cast<double*>(b + L.eig);
+    HIP_TRY(c, hipMemcpyAsync(b + L.cases, &cd, sizeof(CaseDesc), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b + L.order, g_static_order, (size_t)m * np * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b + L.flags, g_static_flags, (size_t)m * sizeof(int), hipMemcpyHostToDevice, s));
+    int* d_it = reinterpret_cast<int*>(b + L.iter);
+    HIP_TRY(c, launch_iter_set(d_it, 0, s));
+    for (int it = 0; it < m; ++it) {
+      std::string e = enqueue_iteration_on(c, reinterpret_cast<const CaseDesc*>(b + L.cases),
+                                           reinterpret_cast<float2*>(b + L.X), d_it, s, false);
+      if (!e.empty()) return fail(c, PTYCHO_E_HIP, e);
+    }
+    HIP_TRY(c, hipMemcpyAsync(g_static_err, b + L.err, (size_t)m * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->t += m;
+    c->pw_par = par;
+    if (err_out) std::memcpy(err_out + done, g_static_err, (size_t)m * sizeof(float));
+    for (int i = 0; i < m; ++i)
+      if (!std::isfinite(g_static_err[i])) {
+        c->failed = true;
+        return fail(c, PTYCHO_E_NUMERIC, "non-finite data error at iteration " + std::to_string(c->t - m + 1 + i));
+      }
+  }
   return PTYCHO_OK;
 }
 
@@ -1004,7 +1214,7 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
   if (d_psi) chk(launch_exit_waves(c->dp, c->db, c->d_dbg_order, B, d_psi, s));
   std::string le;
   if (e == hipSuccess)
-    le = launch_one(c->tm.mask ? c : nullptr, c, c->d_case_dbg, single_shape(c, B), 0, B, c->d_dbg_iter, s);
+    le = launch_one(c->tm.mask ? c : nullptr, c, c->d_case_dbg, c->db.X, single_shape(c, B), 0, B, c->d_dbg_iter, s);
   auto copy = [&](float* dst, const void* src, size_t bytes) {
     if (dst) chk(hipMemcpyAsync(dst, src, bytes, kind_out(mem_kind), s));
   };

@@ -22,7 +22,7 @@ __all__ = [
     "PTYCHO_E_NUMERIC", "PTYCHO_E_STATE", "PTYCHO_FAR_FIELD", "PTYCHO_NEAR_FIELD",
     "PTYCHO_BLUR_AMPLITUDE", "PTYCHO_BLUR_INTENSITY", "PTYCHO_MEM_HOST", "PTYCHO_MEM_DEVICE",
     "PtychoParams", "PtychoError", "lib", "library_path", "load_library", "default_params",
-    "ptycho_init", "ptycho_iterate", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
+    "ptycho_init", "ptycho_iterate", "ptycho_iterate_static", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
     "ptycho_permutation", "ptycho_set_timing", "ptycho_kernel_time", "kernel_names",
     "ptycho_set_graph", "ptycho_set_variant", "ptycho_variant_count", "ptycho_autotune", "ptycho_dft2_bf16", "ptycho_group_create", "ptycho_group_iterate",
@@ -85,6 +85,7 @@ def load_library():
         "ptycho_default_params": (None, [P(PtychoParams)]),
         "ptycho_init": (i32, [P(PtychoParams), fp, fp, fp, fp, i32, vp, P(vp)]),
         "ptycho_iterate": (i32, [vp, i32, fp, fp]),
+        "ptycho_iterate_static": (i32, [vp, i32, fp, fp]),
         "ptycho_get_object": (i32, [vp, fp, i32]),
         "ptycho_get_probe": (i32, [vp, fp, i32]),
         "ptycho_set_state": (i32, [vp, fp, fp, i32, i32]),
@@ -195,6 +196,17 @@ def ptycho_iterate(ctx, n_iter, order=None):
     err = np.zeros(max(int(n_iter), 1), dtype=np.float32)
     st = L.ptycho_iterate(ctx, int(n_iter), _ptr(order, np.int32, PTYCHO_MEM_HOST, keep),
                           ctypes.c_void_p(err.ctypes.data))
+    _check(st, ctx)
+    return err[:n_iter]
+
+
+def ptycho_iterate_static(ctx, n_iter, order=None):
+    """ptycho_iterate with every per-call buffer in the library's static scratch (no allocation)."""
+    L = load_library()
+    keep = []
+    err = np.zeros(max(int(n_iter), 1), dtype=np.float32)
+    st = L.ptycho_iterate_static(ctx, int(n_iter), _ptr(order, np.int32, PTYCHO_MEM_HOST, keep),
+                                 ctypes.c_void_p(err.ctypes.data))
     _check(st, ctx)
     return err[:n_iter]
 
