@@ -327,12 +327,14 @@ def _time_iterations(P, torch, s, cp, steps, graph=True, autotune=True):
     return 1e3 * wall / steps, variant, float(errs[-1])
 
 
-def timed_leg(P, torch, s, cp, steps, warmup, copy_gbs, near):
+def timed_leg(P, torch, s, cp, steps, warmup, copy_gbs, near, variant=None):
     """One workload on one context: autotune, `warmup` iterations, one iteration with events
     around every launch (to find the dominant kernel), then `steps` timed iterations with
     events bound to the dominant kernel's dispatches only.  Inputs are resident in HBM before
-    the timed region.  Returns the throughput, the dominant kernel's roofline and the
-    iteration's graded fraction against the pass model."""
+    the timed region.  `variant` pins a launch variant instead of the autotuner's choice (for
+    hardware-counter runs, under which the tuner's timings are distorted).  Returns the
+    throughput, the dominant kernel's roofline and the iteration's graded fraction against
+    the pass model."""
     dev = torch.device("cuda:0")
     inten = torch.from_numpy(s["intensities"]).to(dev)
     pos = torch.from_numpy(s["positions"]).to(dev)
@@ -343,7 +345,10 @@ def timed_leg(P, torch, s, cp, steps, warmup, copy_gbs, near):
     ctx = P.ptycho_init(cp, inten, pos, probe0, obj0, P.PTYCHO_MEM_DEVICE, stream)
     names = P.kernel_names()
     try:
-        variant = P.ptycho_autotune(ctx, trials=3)
+        if variant is None:
+            variant = P.ptycho_autotune(ctx, trials=3)
+        else:
+            P.ptycho_set_variant(ctx, variant)
         P.ptycho_iterate(ctx, warmup)
         P.ptycho_set_timing(ctx, (1 << len(names)) - 1)
         P.ptycho_iterate(ctx, 1)
@@ -639,6 +644,8 @@ def main():
                     help="first run one plain 256 MiB device-to-device tensor copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
     ap.add_argument("--only-headline", action="store_true", help="time the headline workload only (profiling)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="launch variant of the headline workload instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -662,7 +669,7 @@ def main():
     print(f"[bench] workload generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
     n, k, n_pos = s["n"], s["k"], len(s["positions"])
     cp = make_params(P, s, spec, args.batch)
-    leg = timed_leg(P, torch, s, cp, args.steps, args.warmup, copy_gbs, near=False)
+    leg = timed_leg(P, torch, s, cp, args.steps, args.warmup, copy_gbs, near=False, variant=args.variant)
     out = {
         "metric": "mode-pattern updates/s",
         "value": round(leg["value"], 1),

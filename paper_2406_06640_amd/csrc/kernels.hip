@@ -142,6 +142,7 @@ struct DevBufsG {
   GPtr<float> V, maxv_part, maxw_part;
   GPtr<double> err_part;
   GPtr<double2> cc_part, gram_part;
+  GPtr<unsigned> cov_mask;
   GPtr<float2> vmix;
   GPtr<double> eig;
 };
@@ -163,6 +164,7 @@ __device__ __forceinline__ DevBufsG global_bufs(const DevBufs& in) {
   d.maxw_part = as_global(in.maxw_part);
   d.err_part = as_global(in.err_part);
   d.cc_part = as_global(in.cc_part);
+  d.cov_mask = as_global(in.cov_mask);
   d.gram_part = as_global(in.gram_part);
   d.vmix = as_global(in.vmix);
   d.eig = as_global(in.eig);
@@ -1074,6 +1076,7 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
   const int cnt = tile_list(d, bt.slots, bt.ns, n, r0, c0, tl);
   if (cnt == 0) {
     if (cc_sums && threadIdx.x == 0) d.cc_part[tile] = make_double2(0.0, 0.0);
+    if (cc_sums && threadIdx.x < kObjTile) d.cov_mask[(size_t)tile * kObjTile + threadIdx.x] = 0u;
     return;
   }
   const size_t nn = (size_t)n * n;
@@ -1157,39 +1160,59 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
     }
   }
   if (cc_sums) {
+    // coverage bitmasks of the tile's rows for the constraint pass: a wave holds rows
+    // ty = 2w and 2w + 1 (lanes 0-31 and 32-63) of each group of eight
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) {
+      const int r = r0 + ty + q * kTileRowsPerPass;
+      const unsigned long long m = __ballot(mult[q] > 0 && r < p.h_obj && c < p.w_obj);
+      if (lane == 0) {
+        unsigned* mk = d.cov_mask + (size_t)tile * kObjTile + 2 * w + q * kTileRowsPerPass;
+        mk[0] = (unsigned)m;
+        mk[1] = (unsigned)(m >> 32);
+      }
+    }
     const double2 t = block_sum_d2((double)sa, (double)sp, redd);
     if (threadIdx.x == 0) d.cc_part[tile] = t;
   }
 }
 
-// The complex constraint, Eq. (9)-(10), on one object tile per block: on the
-// tile's pixels that lie in the union of the batch boxes, with C-bar from the
-// partial sums the object update wrote.
+// The complex constraint, Eq. (9)-(10), on kCcTiles object tiles per block: on
+// the tiles' pixels that lie in the union of the batch boxes (the coverage
+// bitmasks the object update wrote), with C-bar of Eq. (11) from the partial
+// sums the object update wrote (reduced once per block).  Every load is issued
+// before the C-bar reduction.  One tile per block: the transcendentals want
+// every wave the machine can hold (four tiles per block was measured slower).
+constexpr int kCcTiles = 1;
 __global__ __launch_bounds__(kThreads) void k_constraint(const CaseDesc* __restrict__ cases, int beta,
                                                          const int* __restrict__ it) {
-  __shared__ TileList tl;
   __shared__ double2 redd[kThreads / 64];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
   const DevBufsG d = global_bufs(bt.cs->d);
-  const int n = p.n;
   const int tiles = tiles_of(p);
-  const int ns = bt.ns;
-  const int tile = blockIdx.x;
-  if (!(bt.flags & FLAG_CC) || tile >= tiles) return;
+  const int tile0 = blockIdx.x * kCcTiles;
+  if (!(bt.flags & FLAG_CC) || tile0 >= tiles) return;
   const int tiles_x = tiles_x_of(p);
-  const int r0 = (tile / tiles_x) * kObjTile, c0 = (tile % tiles_x) * kObjTile;
-  const int cnt = tile_list(d, bt.slots, ns, n, r0, c0, tl);
-  if (cnt == 0) return;
   const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
-  const int c = c0 + tx;
-  // the tile's object values are loaded together with the C-bar partials
-  float2 ov[kTilePix];
+  constexpr int PX = kCcTiles * kTilePix;
+  unsigned rowm[PX];
+  float2 ov[PX];
 #pragma unroll
-  for (int q = 0; q < kTilePix; ++q) {
-    const int r = r0 + ty + q * kTileRowsPerPass;
-    ov[q] = (r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
+  for (int u = 0; u < kCcTiles; ++u) {
+    const int tile = tile0 + u;
+    const bool tv = tile < tiles;
+    const int r0 = (tile / tiles_x) * kObjTile, c = (tile % tiles_x) * kObjTile + tx;
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) {
+      const int rr = ty + q * kTileRowsPerPass;
+      const int r = r0 + rr;
+      rowm[u * kTilePix + q] = tv ? d.cov_mask[(size_t)tile * kObjTile + rr] : 0u;
+      ov[u * kTilePix + q] = (tv && r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c]
+                                                               : make_float2(0.f, 0.f);
+    }
   }
   double sa = 0.0, sp = 0.0;
   for (int i = threadIdx.x; i < tiles; i += kThreads) {
@@ -1204,24 +1227,23 @@ __global__ __launch_bounds__(kThreads) void k_constraint(const CaseDesc* __restr
   const float inv_c = 1.0f / cbar;
   const float a1 = p.alpha1, a2 = p.alpha2;
 #pragma unroll
-  for (int q = 0; q < kTilePix; ++q) {
-    const int r = r0 + ty + q * kTileRowsPerPass;
-    if (r >= p.h_obj || c >= p.w_obj) continue;
-    bool cov = false;
-    for (int i = 0; i < cnt && !cov; ++i) {
-      const int yy = r - tl.pos[i].x, xx = c - tl.pos[i].y;
-      cov = (unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n;
+  for (int u = 0; u < kCcTiles; ++u) {
+    const int tile = tile0 + u;
+    const int r0 = (tile / tiles_x) * kObjTile, c = (tile % tiles_x) * kObjTile + tx;
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) {
+      const int e = u * kTilePix + q;
+      if (!((rowm[e] >> tx) & 1u)) continue;  // outside the union of the boxes (or the object)
+      const int r = r0 + ty + q * kTileRowsPerPass;
+      const float2 o = ov[e];
+      const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
+      const float phi = atan2f(o.y, o.x);
+      const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
+      const float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
+      float sn, cs;
+      sincosf(pc, &sn, &cs);
+      d.obj[(size_t)r * p.w_obj + c] = make_float2(ac * cs, ac * sn);
     }
-    if (!cov) continue;
-    const size_t oi = (size_t)r * p.w_obj + c;
-    const float2 o = ov[q];
-    const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
-    const float phi = atan2f(o.y, o.x);
-    const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
-    const float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
-    float sn, cs;
-    sincosf(pc, &sn, &cs);
-    d.obj[oi] = make_float2(ac * cs, ac * sn);
   }
 }
 
@@ -1731,7 +1753,8 @@ hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int bet
   return hipGetLastError();
 }
 hipError_t launch_constraint(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  pty_launch(k_constraint, dim3(t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  pty_launch(k_constraint, dim3((t.max_tiles + kCcTiles - 1) / kCcTiles, t.n_cases), dim3(kThreads), 0, s, cases,
+             beta, it);
   return hipGetLastError();
 }
 hipError_t launch_gram(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {

@@ -61,6 +61,7 @@ struct DevBufs {
   float* maxw_part;    // per-object-tile max of W
   double* err_part;    // [n_pos][column blocks per frame] data-error partial sums
   double2* cc_part;    // [object tiles] (sum |ln A|, sum |phi|) weighted by box multiplicity
+  unsigned* cov_mask;  // [object tiles][32] row bitmasks of the tile pixels the batch's boxes cover
   double2* gram_part;  // [pairs][kGramBlocks]
   float2* vmix;        // [K][K] eigenvectors (column j = mode j), float
   double* eig;         // [K] eigenvalues

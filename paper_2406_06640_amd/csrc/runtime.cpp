@@ -610,7 +610,7 @@ hipError_t static_scratch_ptr(int dev, void** out) {
 
 // Byte offsets of the buffers of one context inside the static scratch.
 struct StaticLayout {
-  size_t cases, order, flags, err, iter, X, q, dO, nP, V, maxv, maxw, errp, ccp, gramp, vmix, eig, total;
+  size_t cases, order, flags, err, iter, X, q, dO, nP, V, maxv, maxw, errp, ccp, covm, gramp, vmix, eig, total;
   int chunk;  // iterations per staged chunk
 };
 
@@ -642,6 +642,7 @@ StaticLayout static_layout(const ptycho_ctx* c, int n_iter) {
   L.maxw = take(sizeof(float) * (size_t)nobjt);
   L.errp = take(sizeof(double) * (size_t)p.n_pos * nbt);
   L.ccp = take(sizeof(double2) * (size_t)nobjt);
+  L.covm = take(sizeof(unsigned) * (size_t)nobjt * kObjTile);
   L.gramp = take(sizeof(double2) * (K * (K + 1) / 2) * kGramBlocks);
   L.vmix = take(sizeof(float2) * K * K);
   L.eig = take(sizeof(double) * K);
@@ -784,6 +785,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   int2* pos;
   double *errp, *eig;
   double2 *ccp, *gramp;
+  unsigned* covm;
   const int nobjt = n_obj_tiles(dp);
   const int nbt = std::max(max_err_slots(n), p.dft_bf16 ? dft_err_slots(n) : 0);
   ptycho_status st = PTYCHO_OK;
@@ -795,6 +797,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
       (st = dev_alloc(c, &nP, K * nn)) || (st = dev_alloc(c, &V, nn)) ||
       (st = dev_alloc(c, &maxv, (size_t)n_probe_blocks(n))) || (st = dev_alloc(c, &maxw, (size_t)nobjt)) ||
       (st = dev_alloc(c, &errp, (size_t)p.n_pos * nbt)) || (st = dev_alloc(c, &ccp, (size_t)nobjt)) ||
+      (st = dev_alloc(c, &covm, (size_t)nobjt * kObjTile)) ||
       (st = dev_alloc(c, &gramp, (size_t)(K * (K + 1) / 2) * kGramBlocks)) ||
       (st = dev_alloc(c, &vmix, (size_t)K * K)) || (st = dev_alloc(c, &eig, (size_t)K)) ||
       (st = dev_alloc(c, &c->d_iter, 1)) || (st = dev_alloc(c, &c->d_case, 1)) ||
@@ -823,6 +826,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   d.maxw_part = maxw;
   d.err_part = errp;
   d.cc_part = ccp;
+  d.cov_mask = covm;
   d.gram_part = gramp;
   d.vmix = vmix;
   d.eig = eig;
@@ -1067,6 +1071,7 @@ ptycho_status ptycho_iterate_static(ptycho_ctx* c, int32_t n_iter, const int32_t
     cd.d.maxw_part = reinterpret_cast<float*>(b + L.maxw);
     cd.d.err_part = reinterpret_cast<double*>(b + L.errp);
     cd.d.cc_part = reinterpret_cast<double2*>(b + L.ccp);
+    cd.d.cov_mask = reinterpret_cast<unsigned*>(b + L.covm);
     cd.d.gram_part = reinterpret_cast<double2*>(b + L.gramp);
     cd.d.vmix = reinterpret_cast<float2*>(b + L.vmix);
     cd.d.eig = reinterpret_cast<double*>(b + L.eig);
