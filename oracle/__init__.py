@@ -16,6 +16,11 @@ Parity status: every function here is pinned by the CPU tests in
 update for batch size B > 1, which the paper does not define (it is pinned only
 by its B = 1 reduction to sequential ePIE and by convergence): parity unpinned
 for B > 1 beyond those properties.
+
+``oracle.pcdm`` is the FP64 pc-DM engine (the difference map with boxes 1 and
+2, Sec. 4.5), pinned by the least-squares property of its overlap projection,
+the consistent-data fixed point, the single-position reduction to the Fourier
+modulus projection and noise-free convergence (``tests/test_oracle_dm.py``).
 """
 
 from .pcepie import *  # noqa: F401,F403
