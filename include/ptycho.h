@@ -52,6 +52,8 @@ typedef enum {
 enum { PTYCHO_FAR_FIELD = 0, PTYCHO_NEAR_FIELD = 1 };
 enum { PTYCHO_BLUR_AMPLITUDE = 0 /* Eq. (6) */, PTYCHO_BLUR_INTENSITY = 1 /* Eq. (2) */ };
 enum { PTYCHO_MEM_HOST = 0, PTYCHO_MEM_DEVICE = 1 };
+/* Reconstruction engine (Sec. 4.5: the method plugs into ePIE, rPIE and DM). */
+enum { PTYCHO_ENGINE_EPIE = 0 /* pc-ePIE; pc-rPIE through gamma < 1 */, PTYCHO_ENGINE_DM = 1 /* pc-DM */ };
 
 typedef struct ptycho_params {
   /* Frame side n (probe, box and pattern, Fig. 1): 8, 16, 24, 32, 48, 64, 96,
@@ -84,12 +86,31 @@ typedef struct ptycho_params {
    * orthogonalisation stay in FP32.  Results differ from the FP32 path by the
    * split's rounding (about 1e-5 relative per transform). */
   int32_t dft_bf16;
+  /* PTYCHO_ENGINE_EPIE (default) or PTYCHO_ENGINE_DM: the difference map of the
+   * paper's ref. [26] with the blurred modulus projection (box 1) and the complex
+   * constraint (box 2), Sec. 4.5.  The DM state holds one exit wave per scan
+   * position and mode (n_pos x K x n^2 complex64 of device memory), initialised
+   * to P_k o_n.  Each iteration: the overlap projection over every position --
+   * O = (N_O + dm_reg max W O) / (W + dm_reg max W) with
+   * N_O = sum_n sum_k conj(P_k) psi_nk and W = sum_n sum_k |P_k|^2 at the box
+   * offsets, the complex constraint on the union of all boxes inside its windows
+   * (C-bar pooled over every box), then (from probe_update_start) the probe
+   * P_k = (N_P,k + dm_reg max V P_k) / (V + dm_reg max V) with
+   * N_P,k = sum_n conj(o_n) psi_nk, V = sum_n |o_n|^2 -- and the Fourier step
+   * psi_nk += F^-1[M(F(2 z_n - psi_n))]_k - z_nk with z_nk = P_k o_n and M the
+   * blurred modulus constraint; E_t is the data error of the estimates 2 z - psi.
+   * `batch` only sets how many positions share one launch of the Fourier step
+   * (results do not depend on it); modes are not orthogonalised; gamma_obj,
+   * gamma_probe, obj_step, probe_step and dft_bf16 do not apply (dft_bf16 must be 0). */
+  int32_t engine;
+  float dm_reg; /* pc-DM Tikhonov weight of the overlap projection, > 0 (default 1e-3) */
 } ptycho_params;
 
 /* Fill *p with defaults: n = 64, K = 1, far field, sigma 1, kernel 11, amplitude
  * blur, eps 1e-6, alpha1 = 1, alpha2 = 0 (phase object, Sec. 3.1), C-bar in
  * [0.01, 10], constraint off, steps 1, gammas 1, probe update from iteration 1,
- * batch 1, orthogonalisation on, seed 0.  n_pos/obj_h/obj_w are set to 0. */
+ * batch 1, orthogonalisation on, seed 0, the ePIE engine, dm_reg 1e-3.
+ * n_pos/obj_h/obj_w are set to 0. */
 void ptycho_default_params(ptycho_params* p);
 
 /* Create a reconstruction context on the current HIP device.
@@ -142,6 +163,14 @@ ptycho_status ptycho_get_probe(ptycho_ctx* ctx, float* out, int32_t mem_kind);
  * counter to iter >= 0 (resume from a checkpoint).  Clears a failed state. */
 ptycho_status ptycho_set_state(ptycho_ctx* ctx, const float* object, const float* probe,
                                int32_t iter, int32_t mem_kind);
+
+/* pc-DM engine: copy the exit waves [n_pos][K][n][n][2] of every scan position
+ * out of / into the context (host or device per mem_kind), e.g. to checkpoint
+ * the full DM state with ptycho_get_object / ptycho_get_probe.  PTYCHO_E_STATE
+ * for a context of the ePIE engine.  (ptycho_set_state of a DM context resets
+ * the exit waves to P_k o_n of the new object and probe.)  Synchronise the stream. */
+ptycho_status ptycho_get_exit_waves(ptycho_ctx* ctx, float* out, int32_t mem_kind);
+ptycho_status ptycho_set_exit_waves(ptycho_ctx* ctx, const float* in, int32_t mem_kind);
 
 /* Completed-iteration counter of the context (-1 for NULL). */
 int32_t ptycho_iteration(const ptycho_ctx* ctx);

@@ -39,6 +39,8 @@ struct DevParams {
   float eps;
   float alpha1, alpha2, cbar_min, cbar_max;
   float obj_step, probe_step, gamma_obj, gamma_probe;
+  float dm_reg;            // pc-DM: Tikhonov weight delta of the overlap projection (relative to max W, max V)
+  int dm_seg_len;          // pc-DM: scan positions per segment of the probe-numerator partial sums
   float gx[kMaxHalf + 1];  // normalised taps for |dx| = 0..ks_half (x = columns, sigma1)
   float gy[kMaxHalf + 1];  // normalised taps for |dy| = 0..ks_half (y = rows, sigma2)
 };
@@ -62,6 +64,12 @@ struct DevBufs {
   double* err_part;    // [n_pos][column blocks per frame] data-error partial sums
   double2* cc_part;    // [object tiles] (sum |ln A|, sum |phi|) weighted by box multiplicity
   unsigned* cov_mask;  // [object tiles][32] row bitmasks of the tile pixels the batch's boxes cover
+  // pc-DM engine only (null otherwise)
+  float2* psi;         // [n_pos][K][N][N] exit waves of every scan position
+  const int* cov_off;  // [object tiles + 1] offsets into cov_pos
+  const int* cov_pos;  // scan positions whose boxes intersect each object tile, ascending
+  float2* np_part;     // [segments][K][N][N] probe-numerator partial sums
+  float* v_part;       // [segments][N][N] probe-weight partial sums
   double2* gram_part;  // [pairs][kGramBlocks]
   float2* vmix;        // [K][K] eigenvectors (column j = mode j), float
   double* eig;         // [K] eigenvalues
@@ -96,12 +104,13 @@ struct TableShape {
   int max_side_jobs;   // max over cases of object tiles + V blocks
   int col_variant;     // 0..kColVariants-1
   int max_half;        // max over cases of the blur half-width
+  int max_dm_segments; // max over cases of the pc-DM probe-partial segments (0: no pc-DM case)
 };
 
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_CONSTRAINT, KC_GRAM, KC_EIG, KC_REMIX,
-  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_COUNT
+  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_DM_ROWS, KC_DM_OVERLAP, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -140,6 +149,16 @@ hipError_t launch_prepare_amp(const float* inten, float* amp, int n, int n_pos, 
 hipError_t launch_pw(const DevParams& p, const DevBufs& d, int copy, hipStream_t s);
 hipError_t launch_exit_waves(const DevParams& p, const DevBufs& d, const int* slots, int ns, float2* out,
                              hipStream_t s);
+
+// pc-DM engine: the overlap projection over every scan position (object, then
+// probe), the two row passes of its Fourier step for batch `beta` of the
+// positions (the column passes and the modulus factor are the ePIE engine's),
+// and the initial exit waves P_k o_n of every position.
+hipError_t launch_dm_overlap(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
+hipError_t launch_dm_rows_fwd(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_dm_rows_inv(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_dm_init_psi(const DevParams& p, const DevBufs& d, hipStream_t s);
+int dm_segments(int n_pos, int seg_len);
 
 // BF16 matrix-core DFT path (far field, n in {64, 128, 256}); single table only.
 // planes: [4][n][n] bf16 (re_hi, re_lo, im_hi, im_lo) of F[u][x] = exp(-2 pi i u x / n) / sqrt(n).

@@ -159,6 +159,11 @@ std::string validate(const ptycho_params* p) {
   if (p->dft_bf16 != 0 && p->dft_bf16 != 1) return "dft_bf16 must be 0 or 1";
   if (p->dft_bf16 && (p->geometry != PTYCHO_FAR_FIELD || !dft_supported(p->n)))
     return "dft_bf16 needs the far field and n in {64, 128, 256}";
+  if (p->engine != PTYCHO_ENGINE_EPIE && p->engine != PTYCHO_ENGINE_DM) return "bad engine";
+  if (p->engine == PTYCHO_ENGINE_DM) {
+    if (!(finite_f(p->dm_reg) && p->dm_reg > 0)) return "dm_reg must be finite and > 0";
+    if (p->dft_bf16) return "the pc-DM engine runs the FP32 transforms (dft_bf16 must be 0)";
+  }
   return "";
 }
 
@@ -309,9 +314,10 @@ void harvest_timing(ptycho_ctx* c) {
 
 // The seven launches of batch `beta` for every case of a table (five when the
 // fused middle pass replaces fwd_cols, modulus_factor and inv_cols).
-std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
-                         hipStream_t s) {
-  LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
+// The column passes of batch `beta`: forward columns, mode sum, blur, modulus
+// factor, inverse columns (or the fused middle pass).
+std::string launch_middle(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
+                          hipStream_t s) {
   if (fused_active(sh.n, sh.col_variant, sh.max_half)) {
     LAUNCH(tc, KC_COLS_FUSED, s, launch_cols_fused(cases, sh, beta, it, s));
   } else {
@@ -319,6 +325,14 @@ std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape
     LAUNCH(tc, KC_FACTOR, s, launch_factor(cases, sh, beta, it, s));
     LAUNCH(tc, KC_INV_COLS, s, launch_inv_cols(cases, sh, beta, it, s));
   }
+  return "";
+}
+
+std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
+                         hipStream_t s) {
+  LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
+  std::string e = launch_middle(tc, cases, sh, beta, it, s);
+  if (!e.empty()) return e;
   LAUNCH(tc, KC_INV_ROWS, s, launch_inv_rows(cases, sh, beta, it, s));
   LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
   LAUNCH(tc, KC_CONSTRAINT, s, launch_constraint(cases, sh, beta, it, s));
@@ -387,6 +401,7 @@ TableShape single_shape(const ptycho_ctx* c, int max_batch) {
   sh.max_side_jobs = sh.max_tiles + n_probe_blocks(c->prm.n);
   sh.col_variant = c->col_variant;
   sh.max_half = c->dp.ks_half;
+  sh.max_dm_segments = c->prm.engine == PTYCHO_ENGINE_DM ? dm_segments(c->prm.n_pos, c->dp.dm_seg_len) : 0;
   return sh;
 }
 
@@ -461,6 +476,20 @@ std::string enqueue_iteration_on(ptycho_ctx* c, const CaseDesc* cases, float2* X
   const TableShape sh = single_shape(c, c->prm.batch);
   ptycho_ctx* tc = timed ? c : nullptr;
   const int nb = n_batches_of(c->prm);
+  if (c->prm.engine == PTYCHO_ENGINE_DM) {
+    // pc-DM: overlap projection over every position, then the Fourier step batch by batch
+    LAUNCH(tc, KC_DM_OVERLAP, s, launch_dm_overlap(cases, sh, it, s));
+    for (int beta = 0; beta < nb; ++beta) {
+      LAUNCH(tc, KC_DM_ROWS, s, launch_dm_rows_fwd(cases, sh, beta, it, s));
+      std::string e = launch_middle(tc, cases, sh, beta, it, s);
+      if (!e.empty()) return e;
+      LAUNCH(tc, KC_DM_ROWS, s, launch_dm_rows_inv(cases, sh, beta, it, s));
+    }
+    LAUNCH(tc, KC_ERR, s, launch_err_reduce(cases, sh, it, s));
+    hipError_t he = launch_iter_advance(it, s);
+    if (he != hipSuccess) return std::string("iter_advance: ") + hipGetErrorString(he);
+    return "";
+  }
   for (int beta = 0; beta < nb; ++beta) {
     const int ns = std::min(c->prm.batch, c->prm.n_pos - beta * c->prm.batch);
     std::string e = launch_one(tc, c, cases, X, sh, beta, ns, it, s);
@@ -567,6 +596,7 @@ void tune_store_locked(const std::tuple<int, int, int, int>& key, int v) {
 // own copy of the array), resolved once per device and kept in g_static_ptr.
 // ---------------------------------------------------------------------------
 constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kDmSegLen = 64;  // pc-DM: positions per probe-numerator partial sum
 constexpr size_t kStaticOrderInts = (size_t)1 << 18;  // schedule entries staged per chunk of iterations
 constexpr int kStaticMaxChunk = 1024;                 // iterations per chunk
 constexpr int kStaticMaxDevices = 64;
@@ -660,6 +690,8 @@ void ptycho_default_params(ptycho_params* p) {
   p->n = 64;
   p->n_modes = 1;
   p->geometry = PTYCHO_FAR_FIELD;
+  p->engine = PTYCHO_ENGINE_EPIE;
+  p->dm_reg = 1e-3f;
   p->fresnel_px = 0.0;
   p->sigma1 = p->sigma2 = 1.0f;
   p->kernel_size = 11;
@@ -882,6 +914,39 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
     return bail(st);
   INIT_TRY(launch_prepare_amp(raw, amp, n, p.n_pos, p.geometry == PTYCHO_FAR_FIELD, d_bad, d_sum, s));
   INIT_TRY(launch_pw(dp, d, 0, s));
+  if (p.engine == PTYCHO_ENGINE_DM) {
+    // pc-DM: exit-wave state, probe partial sums, and per object tile the ascending
+    // list of positions whose boxes intersect it
+    dp.dm_reg = p.dm_reg;
+    dp.dm_seg_len = kDmSegLen;
+    const int segs = dm_segments(p.n_pos, kDmSegLen);
+    const int tiles_x = (p.obj_w + kObjTile - 1) / kObjTile;
+    std::vector<int> off((size_t)nobjt + 1, 0);
+    auto for_tiles = [&](int i, auto&& fn) {
+      const int r = hpos[2 * i], cc = hpos[2 * i + 1];
+      for (int ty = r / kObjTile; ty <= (r + n - 1) / kObjTile; ++ty)
+        for (int tx = cc / kObjTile; tx <= (cc + n - 1) / kObjTile; ++tx) fn(ty * tiles_x + tx);
+    };
+    for (int i = 0; i < p.n_pos; ++i) for_tiles(i, [&](int t) { ++off[(size_t)t + 1]; });
+    for (int t = 0; t < nobjt; ++t) off[(size_t)t + 1] += off[t];
+    std::vector<int> lst(std::max(off[nobjt], 1)), cur(off.begin(), off.end() - 1);
+    for (int i = 0; i < p.n_pos; ++i) for_tiles(i, [&](int t) { lst[cur[t]++] = i; });
+    int *d_off = nullptr, *d_lst = nullptr;
+    float2 *psi = nullptr, *npp = nullptr;
+    float* vpp = nullptr;
+    if ((st = dev_alloc(c, &d_off, off.size())) || (st = dev_alloc(c, &d_lst, lst.size())) ||
+        (st = dev_alloc(c, &psi, (size_t)p.n_pos * K * nn)) || (st = dev_alloc(c, &npp, (size_t)segs * K * nn)) ||
+        (st = dev_alloc(c, &vpp, (size_t)segs * nn)))
+      return bail(st);
+    INIT_TRY(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(d_lst, lst.data(), lst.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    d.cov_off = d_off;
+    d.cov_pos = d_lst;
+    d.psi = psi;
+    d.np_part = npp;
+    d.v_part = vpp;
+    INIT_TRY(launch_dm_init_psi(dp, d, s));
+  }
   std::vector<int> hb((size_t)p.n_pos * gx);
   std::vector<double> hs((size_t)p.n_pos * gx);
   INIT_TRY(hipMemcpyAsync(hb.data(), d_bad, hb.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -943,7 +1008,9 @@ static ptycho_status fill_schedule(ptycho_ctx* c, int32_t first_it, int32_t n_it
     } else {
       splitmix_perm(c->prm.seed, t, np, row);
     }
-    h_flags[it] = with_pw_parity(case_flags(c->prm, t), par, nb);
+    // pc-DM keeps the probe-power map in copy 0 and does not orthogonalise the modes
+    h_flags[it] = c->prm.engine == PTYCHO_ENGINE_DM ? (case_flags(c->prm, t) & ~FLAG_ORTHO)
+                                                    : with_pw_parity(case_flags(c->prm, t), par, nb);
   }
   return PTYCHO_OK;
 }
@@ -1008,6 +1075,7 @@ ptycho_status ptycho_iterate(ptycho_ctx* c, int32_t n_iter, const int32_t* order
 
 ptycho_status ptycho_iterate_static(ptycho_ctx* c, int32_t n_iter, const int32_t* order, float* err_out) {
   if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->prm.engine != PTYCHO_ENGINE_EPIE) return fail(c, PTYCHO_E_STATE, "ptycho_iterate_static runs the ePIE engine");
   if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
   if (n_iter < 0) return fail(c, PTYCHO_E_INVALID, "n_iter must be >= 0");
   if (n_iter == 0) return PTYCHO_OK;
@@ -1150,9 +1218,35 @@ ptycho_status ptycho_set_state(ptycho_ctx* c, const float* object, const float* 
   if (object)
     HIP_TRY(c, hipMemcpyAsync(c->db.obj, object, (size_t)c->prm.obj_h * c->prm.obj_w * sizeof(float2),
                               kind_in(mem_kind), c->stream));
+  if (c->prm.engine == PTYCHO_ENGINE_DM && (object || probe)) HIP_TRY(c, launch_dm_init_psi(c->dp, c->db, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->t = iter;
   c->failed = false;
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_get_exit_waves(ptycho_ctx* c, float* out, int32_t mem_kind) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->prm.engine != PTYCHO_ENGINE_DM) return fail(c, PTYCHO_E_STATE, "exit waves are state of the pc-DM engine only");
+  if (!out) return fail(c, PTYCHO_E_INVALID, "out is NULL");
+  const size_t count = (size_t)c->prm.n_pos * c->prm.n_modes * c->prm.n * c->prm.n;
+  HIP_TRY(c, hipMemcpyAsync(out, c->db.psi, count * sizeof(float2), kind_out(mem_kind), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_set_exit_waves(ptycho_ctx* c, const float* in, int32_t mem_kind) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->prm.engine != PTYCHO_ENGINE_DM) return fail(c, PTYCHO_E_STATE, "exit waves are state of the pc-DM engine only");
+  if (!in) return fail(c, PTYCHO_E_INVALID, "in is NULL");
+  const size_t count = (size_t)c->prm.n_pos * c->prm.n_modes * c->prm.n * c->prm.n;
+  std::vector<float> h;
+  ptycho_status st = fetch_host(c, in, 2 * count, mem_kind, h);
+  if (st != PTYCHO_OK) return st;
+  for (float x : h)
+    if (!std::isfinite(x)) return fail(c, PTYCHO_E_INVALID, "exit waves contain a non-finite value");
+  HIP_TRY(c, hipMemcpyAsync(c->db.psi, h.data(), count * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PTYCHO_OK;
 }
 
@@ -1162,6 +1256,7 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
                                 float* psi_new, float* factor, float* n_obj, float* w_obj, float* n_probe,
                                 float* v_probe, int32_t mem_kind) {
   if (!c || !idx) return fail(c, PTYCHO_E_INVALID, "NULL argument");
+  if (c->prm.engine != PTYCHO_ENGINE_EPIE) return fail(c, PTYCHO_E_STATE, "debug_step captures a batch of the ePIE engine");
   if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
   if (B < 1 || B > c->prm.batch) return fail(c, PTYCHO_E_INVALID, "B must be in [1, batch]");
   if (t < 1) return fail(c, PTYCHO_E_INVALID, "t must be >= 1");
@@ -1244,6 +1339,7 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
 
 ptycho_status ptycho_autotune(ptycho_ctx* c, int32_t trials, int32_t force, int32_t* chosen) {
   if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->prm.engine != PTYCHO_ENGINE_EPIE) return fail(c, PTYCHO_E_STATE, "the autotuner times the ePIE batch passes");
   if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
   if (trials < 1) trials = 1;
   const int n = c->prm.n;
@@ -1388,6 +1484,8 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
     if (!ctxs[i]) return gfail(nullptr, PTYCHO_E_INVALID, "NULL context in group");
     if (ctxs[i]->failed) return gfail(nullptr, PTYCHO_E_STATE, "a context in the group has failed");
     if (ctxs[i]->prm.dft_bf16) return gfail(nullptr, PTYCHO_E_INVALID, "groups run the FFT path only (dft_bf16 = 0)");
+    if (ctxs[i]->prm.engine != PTYCHO_ENGINE_EPIE)
+      return gfail(nullptr, PTYCHO_E_INVALID, "groups run the ePIE engine (one pc-DM context runs alone)");
     if (ctxs[i]->device != ctxs[0]->device || ctxs[i]->stream != ctxs[0]->stream)
       return gfail(nullptr, PTYCHO_E_INVALID, "group contexts must share one device and stream");
     for (int j = 0; j < i; ++j)

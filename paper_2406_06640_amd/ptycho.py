@@ -21,6 +21,7 @@ __all__ = [
     "PTYCHO_OK", "PTYCHO_E_INVALID", "PTYCHO_E_SHAPE", "PTYCHO_E_OOM", "PTYCHO_E_HIP",
     "PTYCHO_E_NUMERIC", "PTYCHO_E_STATE", "PTYCHO_FAR_FIELD", "PTYCHO_NEAR_FIELD",
     "PTYCHO_BLUR_AMPLITUDE", "PTYCHO_BLUR_INTENSITY", "PTYCHO_MEM_HOST", "PTYCHO_MEM_DEVICE",
+    "PTYCHO_ENGINE_EPIE", "PTYCHO_ENGINE_DM", "ptycho_get_exit_waves", "ptycho_set_exit_waves",
     "PtychoParams", "PtychoError", "lib", "library_path", "load_library", "default_params",
     "ptycho_init", "ptycho_iterate", "ptycho_iterate_static", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
@@ -33,6 +34,7 @@ PTYCHO_OK, PTYCHO_E_INVALID, PTYCHO_E_SHAPE, PTYCHO_E_OOM = 0, -1, -2, -3
 PTYCHO_E_HIP, PTYCHO_E_NUMERIC, PTYCHO_E_STATE = -4, -5, -6
 PTYCHO_FAR_FIELD, PTYCHO_NEAR_FIELD = 0, 1
 PTYCHO_BLUR_AMPLITUDE, PTYCHO_BLUR_INTENSITY = 0, 1
+PTYCHO_ENGINE_EPIE, PTYCHO_ENGINE_DM = 0, 1
 PTYCHO_MEM_HOST, PTYCHO_MEM_DEVICE = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -57,6 +59,7 @@ class PtychoParams(ctypes.Structure):
         ("probe_update_start", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("orthogonalize", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("dft_bf16", ctypes.c_int32),
+        ("engine", ctypes.c_int32), ("dm_reg", ctypes.c_float),
     ]
 
 
@@ -86,6 +89,8 @@ def load_library():
         "ptycho_init": (i32, [P(PtychoParams), fp, fp, fp, fp, i32, vp, P(vp)]),
         "ptycho_iterate": (i32, [vp, i32, fp, fp]),
         "ptycho_iterate_static": (i32, [vp, i32, fp, fp]),
+        "ptycho_get_exit_waves": (i32, [vp, fp, i32]),
+        "ptycho_set_exit_waves": (i32, [vp, fp, i32]),
         "ptycho_get_object": (i32, [vp, fp, i32]),
         "ptycho_get_probe": (i32, [vp, fp, i32]),
         "ptycho_set_state": (i32, [vp, fp, fp, i32, i32]),
@@ -221,6 +226,18 @@ def ptycho_get_probe(ctx, out):
     mk = PTYCHO_MEM_DEVICE if _is_torch(out) else PTYCHO_MEM_HOST
     _check(load_library().ptycho_get_probe(ctx, _out_ptr(out, mk), mk), ctx)
     return out
+
+
+def ptycho_get_exit_waves(ctx, out):
+    """pc-DM exit waves [n_pos][K][n][n] complex64 into `out` (numpy or CUDA tensor)."""
+    mk = PTYCHO_MEM_DEVICE if _is_torch(out) else PTYCHO_MEM_HOST
+    _check(load_library().ptycho_get_exit_waves(ctx, _out_ptr(out, mk), mk), ctx)
+    return out
+
+
+def ptycho_set_exit_waves(ctx, psi, mem_kind=PTYCHO_MEM_HOST):
+    keep = []
+    _check(load_library().ptycho_set_exit_waves(ctx, _ptr(psi, np.complex64, mem_kind, keep), mem_kind), ctx)
 
 
 def _out_ptr(x, mk):
@@ -410,6 +427,14 @@ class Reconstruction:
 
     def set_state(self, obj=None, probe=None, iteration=0):
         ptycho_set_state(self.ctx, obj, probe, iteration)
+
+    def exit_waves(self):
+        n = self.params.n
+        out = np.zeros((self.params.n_pos, self.params.n_modes, n, n), dtype=np.complex64)
+        return ptycho_get_exit_waves(self.ctx, out)
+
+    def set_exit_waves(self, psi):
+        ptycho_set_exit_waves(self.ctx, psi)
 
     def set_graph(self, enable=True):
         ptycho_set_graph(self.ctx, enable)
