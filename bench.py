@@ -414,6 +414,46 @@ def near_field_leg(P, torch, steps, warmup, copy_gbs):
     return leg
 
 
+def dm_leg(P, torch, s, spec, iters, copy_gbs, batch=32):
+    """The pc-DM engine (difference map with boxes 1 and 2, Sec. 4.5) on the headline
+    workload: every iteration projects the object and probe from the exit waves of all
+    1600 positions and runs the Fourier step of every position.  Pass model per position:
+    the exit-wave state read by the object and the probe projections and read and written by
+    the Fourier step (32 K N^2 bytes), the pattern and box (12 N^2), and one global round trip
+    of the K frames per propagation direction (32 K N^2)."""
+    dev = torch.device("cuda:0")
+    n, k, n_pos = s["n"], s["k"], len(s["positions"])
+    cp = make_params(P, s, spec, batch)
+    cp.engine = P.PTYCHO_ENGINE_DM
+    inten = torch.from_numpy(s["intensities"]).to(dev)
+    pos = torch.from_numpy(s["positions"]).to(dev)
+    probe0 = torch.from_numpy(s["probe0"].astype(np.complex64)).to(dev)
+    obj0 = torch.from_numpy(s["obj0"].astype(np.complex64)).to(dev)
+    names = P.kernel_names()
+    with P.Reconstruction(cp, inten, pos, probe0, obj0, mem_kind=P.PTYCHO_MEM_DEVICE) as r:
+        r.iterate(1)
+        P.ptycho_set_timing(r.ctx, (1 << len(names)) - 1)
+        r.iterate(1)
+        P.ptycho_set_timing(r.ctx, 0)
+        prof = {nm: P.ptycho_kernel_time(r.ctx, i, reset=True) for i, nm in enumerate(names)}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs = r.iterate(iters)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ms = 1e3 * wall / iters
+    nn = n * n
+    flop = n_pos * (k * 2 * 5 * nn * 2 * math.log2(n) + (30 * k + 60) * nn)
+    model = {"flop": float(flop), "bytes_min": int(n_pos * (32 * k + 12) * nn),
+             "bytes_pass": int(n_pos * (64 * k + 12) * nn)}
+    return {"workload": "pc-DM on the far-field 1024^2 / 256^2 / K=4 / 1600-position workload, overlap projection "
+                        f"over every position, Fourier step in launches of {batch} positions, constraint every "
+                        "iteration", "iterations": iters, "value": round(n_pos * k * iters / wall, 1),
+            "unit": "mode-pattern updates/s", "ms_per_iteration": round(ms, 3), "graded": graded(model, ms, copy_gbs),
+            "kernel_ms_per_iteration": {nm: round(v, 4) for nm, (v, c) in prof.items() if c},
+            "final_data_error": float(errs[-1])}
+
+
 def group_leg(P, torch, iters, copy_gbs, n_cases=64):
     """The 64-case batched workload (N in {64,128,192,256}, 100-2500 positions, 1-8 modes, batch
     32, seeds [1004, i]; patterns made on the GPU) advanced as one group with graph replay:
@@ -632,6 +672,8 @@ def main():
                     help="skip the near-field 1536^2 / 512^2 / K=8 workload")
     ap.add_argument("--near-field-steps", type=int, default=5)
     ap.add_argument("--no-group", action="store_true", help="skip the 64-case workload as one group")
+    ap.add_argument("--no-dm", action="store_true", help="skip the pc-DM engine leg")
+    ap.add_argument("--dm-iterations", type=int, default=3)
     ap.add_argument("--group-iterations", type=int, default=3)
     ap.add_argument("--batched", action="store_true",
                     help="also run the 64-case batched workload's full comparison: group vs the cases one by "
@@ -699,6 +741,9 @@ def main():
         if not args.no_near_field:
             print("[bench] near-field workload", file=sys.stderr, flush=True)
             out["near_field"] = near_field_leg(P, torch, args.near_field_steps, args.warmup, copy_gbs)
+        if not args.no_dm:
+            print("[bench] pc-DM engine on the headline workload", file=sys.stderr, flush=True)
+            out["dm"] = dm_leg(P, torch, s, spec, args.dm_iterations, copy_gbs)
         if not args.no_group:
             print("[bench] 64-case workload as one group", file=sys.stderr, flush=True)
             out["group"] = group_leg(P, torch, args.group_iterations, copy_gbs)
