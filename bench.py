@@ -454,6 +454,36 @@ def dm_leg(P, torch, s, spec, iters, copy_gbs, batch=32):
             "final_data_error": float(errs[-1])}
 
 
+def c1_leg(P, torch, iters=50):
+    """The 64^2-frame far-field scan (144^2 object, 10 x 10 raster at 8 px, K = 1, 1e5 counts) at
+    batch size 1 -- the paper's sequential loop, 100 dependent updates per iteration -- with the
+    sequential kernel (one workgroup runs the whole iteration) and with the batch passes (six
+    launches per position), both replayed from a captured graph."""
+    import datagen
+    spec = datagen.CONFIGS["far64"]
+    s = datagen.make_scan(spec, spec["seed"])
+    n_pos = len(s["positions"])
+    out = {"workload": "far field, object 144x144, frames 64x64, 10x10 raster at 8 px (100 positions), K=1, "
+                       "sigma 1, Poisson 1e5; batch 1 (sequential updates), constraint on every iteration",
+           "iterations": iters}
+    for name, variant in (("sequential_kernel", P.ptycho_variant_count() - 1), ("batch_passes", 1)):
+        cp = make_params(P, s, spec, 1)
+        with P.Reconstruction(cp, s["intensities"], s["positions"], s["probe0"].astype(np.complex64),
+                              s["obj0"].astype(np.complex64)) as r:
+            r.set_variant(variant)
+            r.set_graph(True)
+            r.iterate(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.iterate(iters)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        out[name] = {"ms_per_iteration": round(1e3 * wall / iters, 4),
+                     "us_per_position": round(1e6 * wall / iters / n_pos, 2),
+                     "updates_per_s": round(n_pos * iters / wall, 1)}
+    return out
+
+
 def group_leg(P, torch, iters, copy_gbs, n_cases=64):
     """The 64-case batched workload (N in {64,128,192,256}, 100-2500 positions, 1-8 modes, batch
     32, seeds [1004, i]; patterns made on the GPU) advanced as one group with graph replay:
@@ -673,6 +703,7 @@ def main():
     ap.add_argument("--near-field-steps", type=int, default=5)
     ap.add_argument("--no-group", action="store_true", help="skip the 64-case workload as one group")
     ap.add_argument("--no-dm", action="store_true", help="skip the pc-DM engine leg")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 64^2-frame batch-1 leg")
     ap.add_argument("--dm-iterations", type=int, default=3)
     ap.add_argument("--group-iterations", type=int, default=3)
     ap.add_argument("--batched", action="store_true",
@@ -741,6 +772,9 @@ def main():
         if not args.no_near_field:
             print("[bench] near-field workload", file=sys.stderr, flush=True)
             out["near_field"] = near_field_leg(P, torch, args.near_field_steps, args.warmup, copy_gbs)
+        if not args.no_c1:
+            print("[bench] 64^2 scan at batch 1 (sequential kernel vs batch passes)", file=sys.stderr, flush=True)
+            out["c1_batch1"] = c1_leg(P, torch)
         if not args.no_dm:
             print("[bench] pc-DM engine on the headline workload", file=sys.stderr, flush=True)
             out["dm"] = dm_leg(P, torch, s, spec, args.dm_iterations, copy_gbs)

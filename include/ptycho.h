@@ -196,10 +196,16 @@ ptycho_status ptycho_debug_step(ptycho_ctx* ctx, const int32_t* idx, int32_t B, 
  * Not used while per-kernel timing is on. */
 ptycho_status ptycho_set_graph(ptycho_ctx* ctx, int32_t enable);
 
-/* Launch variants of the FFT passes: variant v (0 .. ptycho_variant_count()-1)
+/* Launch variants of the FFT passes: variant v (0 .. ptycho_variant_count()-2)
  * uses column blocks of COLS/2, COLS or 2 COLS columns (v % 3; COLS is the
  * default width for n), runs the inverse column pass with one workgroup per
  * mode when (v / 3) & 1 and the first row pass likewise when (v / 6) & 1.
+ * The last variant (ptycho_variant_count()-1) is the sequential kernel: one
+ * workgroup runs each whole iteration (every position of Fig. 1's loop in
+ * order, the updates applied in between), for batch 1 on far-field frames of
+ * side 16, 32, 48 or 64; it is the default there (the autotuner keeps it), and
+ * groups run such cases one workgroup per case in one launch.  Its results
+ * agree with the batch passes to FP32 rounding, not bitwise.
  * Variants other than the three widths exist for n in {64, 128, 192, 256, 512}.
  * The object and probe after any iteration are bitwise identical for every
  * variant (the data error E_t is summed in a different grouping for other

@@ -36,7 +36,7 @@ namespace pty {
 const char* const kKernelNames[KC_COUNT] = {
     "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_probe_update", "complex_constraint",
     "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor", "cols_fused",
-    "dm_rows", "dm_overlap"};
+    "dm_rows", "dm_overlap", "seq_iteration"};
 
 LaunchEvents& launch_events() {
   thread_local LaunchEvents ev;
@@ -1171,7 +1171,10 @@ __global__ __launch_bounds__(kThreads) void k_remix(const CaseDesc* __restrict__
     d.probe[(size_t)j * nn + pix] = s;
     pw += s.x * s.x + s.y * s.y;
   }
-  d.pw[(size_t)pw_copy(cs->flags[*it_ptr], cs->n_batches) * nn + pix] = pw;  // read by the next iteration
+  // both copies of the probe-power map: the next iteration's first batch reads one, and its probe
+  // update (or, without one, nothing) writes the other before any batch reads it
+  d.pw[pix] = pw;
+  d.pw[nn + pix] = pw;
 }
 
 // One 1024-thread block per case (the partials of a whole iteration are few

@@ -110,7 +110,7 @@ struct TableShape {
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_CONSTRAINT, KC_GRAM, KC_EIG, KC_REMIX,
-  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_DM_ROWS, KC_DM_OVERLAP, KC_COUNT
+  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_DM_ROWS, KC_DM_OVERLAP, KC_SEQ, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -159,6 +159,11 @@ hipError_t launch_dm_rows_fwd(const CaseDesc* cases, const TableShape& t, int be
 hipError_t launch_dm_rows_inv(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_dm_init_psi(const DevParams& p, const DevBufs& d, hipStream_t s);
 int dm_segments(int n_pos, int seg_len);
+
+// Sequential pc-ePIE for batch size 1 and small far-field frames: one
+// workgroup per case runs a whole iteration (every position in order).
+bool seq_supported(int n, bool near_field);
+hipError_t launch_seq_iter(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
 
 // BF16 matrix-core DFT path (far field, n in {64, 128, 256}); single table only.
 // planes: [4][n][n] bf16 (re_hi, re_lo, im_hi, im_lo) of F[u][x] = exp(-2 pi i u x / n) / sqrt(n).

@@ -72,6 +72,7 @@ struct ptycho_ctx {
   int* d_dbg_iter = nullptr;
   float* d_dbg_err = nullptr;
   int col_variant = 1;
+  bool seq = false;          // whole iterations in the sequential kernel (batch 1, small far-field frames)
   void* d_planes = nullptr;  // bf16 DFT table planes (dft_bf16 path)
   // graph replay of one iteration
   bool use_graph = false;
@@ -86,6 +87,7 @@ struct ptycho_group {
   struct Table {
     TableShape shape{};
     std::vector<int> members;  // indices into ctx
+    bool seq = false;          // members run whole iterations in the sequential kernel
     CaseDesc* d_cases = nullptr;
     CaseDesc* h_cases = nullptr;  // pinned
   };
@@ -375,6 +377,14 @@ int case_flags(const ptycho_params& p, int t) {
 
 int n_batches_of(const ptycho_params& p) { return (p.n_pos + p.batch - 1) / p.batch; }
 
+// The sequential kernel runs ePIE iterations of batch size 1 on small far-field frames.
+bool seq_eligible(const ptycho_params& p) {
+  return p.batch == 1 && !p.dft_bf16 && p.engine == PTYCHO_ENGINE_EPIE &&
+         seq_supported(p.n, p.geometry == PTYCHO_NEAR_FIELD);
+}
+// Launch variant index of the sequential kernel (after the batch-pass variants).
+constexpr int kSeqVariant = kColVariants;
+
 // Fill the per-case fields of a table entry for the current call.
 void fill_case(const ptycho_ctx* c, CaseDesc& cd, const int* order, const int* flags, float* err) {
   cd.p = c->dp;
@@ -490,10 +500,14 @@ std::string enqueue_iteration_on(ptycho_ctx* c, const CaseDesc* cases, float2* X
     if (he != hipSuccess) return std::string("iter_advance: ") + hipGetErrorString(he);
     return "";
   }
-  for (int beta = 0; beta < nb; ++beta) {
-    const int ns = std::min(c->prm.batch, c->prm.n_pos - beta * c->prm.batch);
-    std::string e = launch_one(tc, c, cases, X, sh, beta, ns, it, s);
-    if (!e.empty()) return e;
+  if (c->seq) {
+    LAUNCH(tc, KC_SEQ, s, launch_seq_iter(cases, sh, it, s));
+  } else {
+    for (int beta = 0; beta < nb; ++beta) {
+      const int ns = std::min(c->prm.batch, c->prm.n_pos - beta * c->prm.batch);
+      std::string e = launch_one(tc, c, cases, X, sh, beta, ns, it, s);
+      if (!e.empty()) return e;
+    }
   }
   std::string e = launch_end(tc, cases, sh, it, s);
   if (!e.empty()) return e;
@@ -971,6 +985,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
     tune_load_locked();
     auto it = g_tune.find(std::make_tuple(n, K, B, (int)p.geometry));
     if (it != g_tune.end() && col_variant_valid(n, it->second)) c->col_variant = it->second;
+    c->seq = seq_eligible(p);
   }
   *out = c;
   return PTYCHO_OK;
@@ -1167,10 +1182,19 @@ ptycho_status ptycho_iterate_static(ptycho_ctx* c, int32_t n_iter, const int32_t
   return PTYCHO_OK;
 }
 
-int32_t ptycho_variant_count(void) { return kColVariants; }
+int32_t ptycho_variant_count(void) { return kColVariants + 1; }
 
 ptycho_status ptycho_set_variant(ptycho_ctx* c, int32_t variant) {
   if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (variant == kSeqVariant) {
+    if (!seq_eligible(c->prm))
+      return fail(c, PTYCHO_E_INVALID, "the sequential kernel runs batch 1 on far-field frames of side 16, 32, 48 or 64");
+    if (!c->seq) drop_graph(c);
+    c->seq = true;
+    return PTYCHO_OK;
+  }
+  if (c->seq) drop_graph(c);
+  c->seq = false;
   if (!col_variant_valid(c->prm.n, variant))
     return fail(c, PTYCHO_E_INVALID, "launch variant " + std::to_string(variant) + " does not exist for n = " +
                                          std::to_string(c->prm.n));
@@ -1340,6 +1364,10 @@ ptycho_status ptycho_debug_step(ptycho_ctx* c, const int32_t* idx, int32_t B, in
 ptycho_status ptycho_autotune(ptycho_ctx* c, int32_t trials, int32_t force, int32_t* chosen) {
   if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
   if (c->prm.engine != PTYCHO_ENGINE_EPIE) return fail(c, PTYCHO_E_STATE, "the autotuner times the ePIE batch passes");
+  if (c->seq) {  // one launch per iteration: nothing to tune
+    if (chosen) *chosen = kSeqVariant;
+    return PTYCHO_OK;
+  }
   if (c->failed) return fail(c, PTYCHO_E_STATE, "context failed earlier: " + c->err);
   if (trials < 1) trials = 1;
   const int n = c->prm.n;
@@ -1495,13 +1523,14 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
   g->ctx.assign(ctxs, ctxs + n);
   g->stream = ctxs[0]->stream;
   // one table per (frame size, geometry)
-  std::map<std::pair<int, int>, int> idx;
+  std::map<std::tuple<int, int, int>, int> idx;
   for (int i = 0; i < n; ++i) {
     const ptycho_ctx* c = ctxs[i];
-    const auto key = std::make_pair(c->prm.n, (int)c->prm.geometry);
+    const auto key = std::make_tuple(c->prm.n, (int)c->prm.geometry, c->seq ? 1 : 0);
     if (!idx.count(key)) {
       idx[key] = (int)g->tables.size();
       g->tables.emplace_back();
+      g->tables.back().seq = c->seq;
       TableShape& sh = g->tables.back().shape;
       sh.n = c->prm.n;
       sh.near_field = c->prm.geometry == PTYCHO_NEAR_FIELD;
@@ -1549,8 +1578,14 @@ namespace {
 // One iteration of every member: batches in lockstep over the tables, then
 // each table's end-of-iteration work, then the iteration counter.
 std::string enqueue_group_iteration(ptycho_group* g, hipStream_t s) {
+  for (auto& tb : g->tables)
+    if (tb.seq) {  // whole iterations of every member, one workgroup per case
+      const hipError_t he = launch_seq_iter(tb.d_cases, tb.shape, g->d_iter, s);
+      if (he != hipSuccess) return std::string("seq_iteration: ") + hipGetErrorString(he);
+    }
   for (int beta = 0; beta < g->max_nb; ++beta)
     for (auto& tb : g->tables) {
+      if (tb.seq) continue;
       std::string e = launch_batch(nullptr, tb.d_cases, tb.shape, beta, g->d_iter, s);
       if (!e.empty()) return e;
     }
@@ -1633,7 +1668,7 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
       f = with_pw_parity(f, par, nb);
     }
     c->pw_par_next = par;
-    max_nb = std::max(max_nb, n_batches_of(c->prm));
+    if (!c->seq) max_nb = std::max(max_nb, n_batches_of(c->prm));
   }
   for (auto& tb : g->tables)
     for (size_t m = 0; m < tb.members.size(); ++m) {

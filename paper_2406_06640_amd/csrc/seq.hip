@@ -1,0 +1,305 @@
+// Sequential pc-ePIE for small frames (gfx950): one workgroup runs a whole
+// iteration of one reconstruction with batch size 1 -- the loop of Fig. 1 over
+// the iteration's positions, each update applied before the next position
+// starts -- so the per-position chain costs one launch's worth of work instead
+// of seven launches.  A table of independent reconstructions runs one
+// workgroup per case in the same launch.
+//
+// Per position (box o at r_n, K modes, frames of side N <= 64 kept in LDS):
+//   exit waves o P_k, 2D transform (rows then columns, each 1D pass scaled by
+//   N^-1/2: the unitary DFT of Eq. 1) of every mode, Psi_k parked in the work
+//   frames X[0][k]; the incoherent mode sum, the separable Gaussian blur of the
+//   amplitude (Eq. 6) or the intensity (Eq. 2), vertical then horizontal, the
+//   modulus factor and the position's data error (box 1); per mode
+//   Psi' = f Psi_k, inverse transform, dpsi = psi' - o P_k, the object
+//   numerator sum_k conj(P_k) dpsi_k and the probe update
+//   P_k += beta conj(o) dpsi_k / ((1 - g) |o|^2 + g max |o|^2) from the
+//   pre-update box; then O += alpha N_O / ((1 - g) W + g max W) over the box
+//   with W = sum_k |P_k|^2 of the pre-update probe; inside a constraint window
+//   the complex constraint of Eq. (9)-(11) over the box.  The same arithmetic
+//   as a batch of one position on the batch passes, in one workgroup.
+// Global memory written by one position (object, probe, parked frames) is read
+// by the next only after a workgroup barrier, which orders it for the waves of
+// the workgroup (they share one CU and its L1).
+#include "kernels_dev.hpp"
+
+namespace pty {
+
+bool seq_supported(int n, bool near_field) {
+  return !near_field && (n == 16 || n == 32 || n == 48 || n == 64);
+}
+
+template <int N>
+struct SeqLds {
+  using RowF = Frame<N, N, false>;
+  using ColF = Frame<N, N, true>;
+  static constexpr int ROW = RowF::ELEMS;  // float2, row-pass layout
+  static constexpr int COL = ColF::ELEMS;  // float2, column-pass layout
+  // tw [N] | row buffer | column buffer | box [N^2] float2 | factor [N^2] float
+  static constexpr size_t BYTES =
+      sizeof(float2) * ((size_t)N + ROW + COL + (size_t)N * N) + sizeof(float) * (size_t)N * N;
+};
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restrict__ cases, const int* __restrict__ it_ptr) {
+  using RowF = Frame<N, N, false>;
+  using ColF = Frame<N, N, true>;
+  constexpr int SR = RegShape<N, N>::STORE_SLOTS;
+  constexpr int LR = RegShape<N, N>::LOAD_SLOTS;
+  constexpr int NN = N * N;
+  constexpr int EP = (NN + kThreads - 1) / kThreads;  // plain elements per thread
+  extern __shared__ float2 sm[];
+  __shared__ double red[kThreads / 64];
+  __shared__ double2 redd[kThreads / 64];
+  __shared__ float redf[kThreads / 64];
+  __shared__ float sgx[kMaxHalf + 1], sgy[kMaxHalf + 1];
+  const CaseDesc* cs = cases + blockIdx.y;
+  const DevParams& p = cs->p;
+  const DevBufsG d = global_bufs(cs->d);
+  const int it = *it_ptr;
+  const int flags = cs->flags[it];
+  const int np = cs->n_pos;
+  const int* order = cs->order + (size_t)it * np;
+  float2* tw = sm;
+  float2* rowbuf = sm + N;
+  float2* colbuf = rowbuf + SeqLds<N>::ROW;
+  float2* obox = colbuf + SeqLds<N>::COL;
+  float* fbuf = reinterpret_cast<float*>(obox + NN);
+  float* t0 = reinterpret_cast<float*>(rowbuf);  // blur buffers, free between the transforms
+  float* t1 = reinterpret_cast<float*>(colbuf);
+  for (int i = threadIdx.x; i < N; i += kThreads) tw[i] = d.tw[i];
+  if (threadIdx.x <= kMaxHalf) {
+    sgx[threadIdx.x] = p.gx[threadIdx.x];
+    sgy[threadIdx.x] = p.gy[threadIdx.x];
+  }
+  const int K = p.k, W = p.w_obj, h = p.ks_half;
+  const float scale = rsqrtf((float)N);
+  const bool inten = p.blur_intensity != 0;
+  const bool probe_upd = (flags & FLAG_PROBE) != 0;
+  const int err_slots = cs->n_err_part / np;
+  float2* X = d.X;
+  __syncthreads();
+  for (int step = 0; step < np; ++step) {
+    const int pat = order[step];
+    const int2 rc = d.pos[pat];
+    // box into LDS (row-major) and its largest |o|^2
+    float vmax = 0.f;
+    for (int e = threadIdx.x; e < NN; e += kThreads) {
+      const int y = e / N, x = e - y * N;
+      const float2 o = d.obj[(size_t)(rc.x + y) * W + rc.y + x];
+      obox[e] = o;
+      vmax = fmaxf(vmax, o.x * o.x + o.y * o.y);
+    }
+    vmax = block_max_f(vmax, redf);  // also: the box is visible to every thread
+    // forward transforms of every mode; |Psi_k|^2 summed in the column pass's store slots
+    float acc[SR];
+#pragma unroll
+    for (int i = 0; i < SR; ++i) acc[i] = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float2* pk = d.probe + (size_t)k * NN;
+      float2* xk = X + (size_t)k * NN;
+      float2 v[LR];
+      auto load_row = [&](int s, int y, int x) { return cmul(obox[y * N + x], pk[y * N + x]); };
+      fft_gather<N, N, false>(v, load_row);
+      fft_first<N, N, false, false>(v, rowbuf);
+      auto to_col = [&](int s, int y, int u, float2 z) { colbuf[ColF::lidx(u, y)] = cscale(z, scale); };
+      fft_rest<N, N, false, false>(v, rowbuf, tw, to_col);
+      __syncthreads();  // every row-pass output is in the column buffer
+      auto from_col = [&](int s, int u, int y) { return colbuf[ColF::lidx(u, y)]; };
+      auto park = [&](int s, int u, int y, float2 z) {
+        z = cscale(z, scale);
+        xk[y * N + u] = z;
+        acc[s] += z.x * z.x + z.y * z.y;
+      };
+      fft_reg<N, N, true, false, true>(colbuf, tw, from_col, park);
+      __syncthreads();  // the column buffer is read before the next mode rewrites it
+    }
+    // box 1: mode sum -> blur (vertical, then horizontal) -> modulus factor; data error
+    for_store_slots<N, N, true>([&](int s, int u, int y) { t0[y * N + u] = inten ? acc[s] : sqrtf(acc[s]); });
+    __syncthreads();
+    {
+      float gv[EP];
+#pragma unroll
+      for (int j = 0; j < EP; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        gv[j] = (NN % kThreads != 0 && e >= NN) ? 0.f : sgy[0] * t0[e];
+      }
+      for (int dy = 1; dy <= h; ++dy) {
+        const float gd = sgy[dy];
+#pragma unroll
+        for (int j = 0; j < EP; ++j) {
+          const int e = threadIdx.x + j * kThreads;
+          if (NN % kThreads != 0 && e >= NN) continue;
+          const int y = e / N, x = e - y * N;
+          gv[j] += gd * (t0[wrap(y - dy, N) * N + x] + t0[wrap(y + dy, N) * N + x]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < EP; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (NN % kThreads == 0 || e < NN) t1[e] = gv[j];
+      }
+    }
+    __syncthreads();
+    double err = 0.0;
+    {
+      const float* amp = d.amp + (size_t)pat * NN;
+      float gv[EP];
+#pragma unroll
+      for (int j = 0; j < EP; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        gv[j] = (NN % kThreads != 0 && e >= NN) ? 0.f : sgx[0] * t1[e];
+      }
+      for (int dx = 1; dx <= h; ++dx) {
+        const float gd = sgx[dx];
+#pragma unroll
+        for (int j = 0; j < EP; ++j) {
+          const int e = threadIdx.x + j * kThreads;
+          if (NN % kThreads != 0 && e >= NN) continue;
+          const int x = e % N;
+          const float* row = t1 + (e - x);
+          gv[j] += gd * (row[wrap(x - dx, N)] + row[wrap(x + dx, N)]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < EP; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (NN % kThreads != 0 && e >= NN) continue;
+        const float a = amp[e];
+        float ag, f;
+        if (inten) {
+          ag = sqrtf(gv[j]);
+          f = a / sqrtf(gv[j] + p.eps * p.eps);
+        } else {
+          ag = gv[j];
+          f = a / (gv[j] + p.eps);
+        }
+        fbuf[e] = f;
+        const double dd = (double)a - (double)ag;
+        err += dd * dd;
+      }
+    }
+    const double etot = block_sum_d(err, red);  // also: fbuf and the blur buffers are settled
+    if (threadIdx.x < err_slots) d.err_part[(size_t)pat * err_slots + threadIdx.x] = threadIdx.x == 0 ? etot : 0.0;
+    // inverse transforms; object numerator, probe update
+    float2 num[SR];
+    float pw[SR];
+#pragma unroll
+    for (int i = 0; i < SR; ++i) {
+      num[i] = make_float2(0.f, 0.f);
+      pw[i] = 0.f;
+    }
+    for (int k = 0; k < K; ++k) {
+      float2* pk = d.probe + (size_t)k * NN;
+      const float2* xk = X + (size_t)k * NN;
+      auto load_icol = [&](int s, int u, int y) {
+        const float2 z = xk[y * N + u];
+        const float f = fbuf[y * N + u];
+        return make_float2(z.x * f, z.y * f);  // no contraction anywhere in this file (fft_lds.hpp)
+      };
+      auto to_row = [&](int s, int u, int y, float2 z) { rowbuf[RowF::lidx(y, u)] = cscale(z, scale); };
+      fft_reg<N, N, true, true>(colbuf, tw, load_icol, to_row);
+      __syncthreads();  // every column-pass output is in the row buffer
+      auto from_row = [&](int s, int y, int x) { return rowbuf[RowF::lidx(y, x)]; };
+      auto update = [&](int s, int y, int x, float2 z) {
+        const int e = y * N + x;
+        const float2 psi_new = cscale(z, scale);
+        const float2 o = obox[e];
+        const float2 pv = pk[e];
+        const float2 dpsi = csub(psi_new, cmul(o, pv));
+        num[s] = cadd(num[s], cmulc(dpsi, pv));
+        pw[s] += pv.x * pv.x + pv.y * pv.y;
+        if (probe_upd) {
+          const float den = (1.0f - p.gamma_probe) * (o.x * o.x + o.y * o.y) + p.gamma_probe * vmax;
+          if (den > 0.f) {
+            const float sc = p.probe_step / den;
+            const float2 c = cmulc(dpsi, o);
+            pk[e] = make_float2(pv.x + sc * c.x, pv.y + sc * c.y);
+          }
+        }
+      };
+      fft_reg<N, N, false, true, true>(rowbuf, tw, from_row, update);
+      __syncthreads();  // the row buffer is read before the next mode rewrites it
+    }
+    // object update over the box (denominators from the pre-update probe power)
+    float wmax = 0.f;
+#pragma unroll
+    for (int i = 0; i < SR; ++i) wmax = fmaxf(wmax, pw[i]);
+    wmax = block_max_f(wmax, redf);
+    const bool cc = (flags & FLAG_CC) != 0;
+    float sa = 0.f, sp = 0.f;
+    float2 onew[SR];
+    for_store_slots<N, N, false>([&](int s, int y, int x) {
+      const int e = y * N + x;
+      float2 o = obox[e];
+      const float den = (1.0f - p.gamma_obj) * pw[s] + p.gamma_obj * wmax;
+      if (den > 0.f) {
+        const float sc = p.obj_step / den;
+        o.x += sc * num[s].x;
+        o.y += sc * num[s].y;
+        d.obj[(size_t)(rc.x + y) * W + rc.y + x] = o;
+      }
+      onew[s] = o;
+      if (cc) {
+        const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
+        sa += fabsf(logf(a));
+        sp += fabsf(atan2f(o.y, o.x));
+      }
+    });
+    if (cc) {
+      // box 2: C-bar of Eq. (11) over the box, then Eq. (9)-(10)
+      const double2 tot = block_sum_d2((double)sa, (double)sp, redd);
+      if (tot.y > 0.0) {
+        float cbar = (float)(tot.x / tot.y);
+        cbar = fminf(fmaxf(cbar, p.cbar_min), p.cbar_max);
+        const float inv_c = 1.0f / cbar;
+        const float a1 = p.alpha1, a2 = p.alpha2;
+        for_store_slots<N, N, false>([&](int s, int y, int x) {
+          const float2 o = onew[s];
+          const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
+          const float phi = atan2f(o.y, o.x);
+          const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
+          const float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
+          float sn, cs2;
+          sincosf(pc, &sn, &cs2);
+          d.obj[(size_t)(rc.x + y) * W + rc.y + x] = make_float2(ac * cs2, ac * sn);
+        });
+      }
+    }
+    __syncthreads();  // object, probe and LDS settled before the next position
+  }
+  // the probe-power map sum_k |P_k|^2 of the final probe, both copies (batch passes read it)
+  for (int e = threadIdx.x; e < NN; e += kThreads) {
+    float s2 = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float2 v = d.probe[(size_t)k * NN + e];
+      s2 += v.x * v.x + v.y * v.y;
+    }
+    d.pw[e] = s2;
+    d.pw[(size_t)NN + e] = s2;
+  }
+}
+
+template <int N>
+static hipError_t seq_t(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
+  // more than 64 KiB of dynamic LDS for N = 64: allowed once per instantiation
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(k_seq_iter<N>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)SeqLds<N>::BYTES);
+  if (attr != hipSuccess) return attr;
+  pty_launch(k_seq_iter<N>, dim3(1, t.n_cases), dim3(kThreads), SeqLds<N>::BYTES, s, cases, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_seq_iter(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s) {
+  if (t.near_field) return hipErrorInvalidValue;
+  switch (t.n) {
+    case 16: return seq_t<16>(cases, t, it, s);
+    case 32: return seq_t<32>(cases, t, it, s);
+    case 48: return seq_t<48>(cases, t, it, s);
+    case 64: return seq_t<64>(cases, t, it, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pty

@@ -105,7 +105,8 @@ def test_null_context_calls_fail_cleanly():
 
 def test_variant_api_host_side():
     import paper_2406_06640_amd as P
-    assert P.ptycho_variant_count() == 18
+    # 18 batch-pass variants and the sequential kernel
+    assert P.ptycho_variant_count() == 19
     assert P.load_library().ptycho_set_variant(None, 1) == P.PTYCHO_E_INVALID
 
 
