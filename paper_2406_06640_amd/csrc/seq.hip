@@ -7,8 +7,8 @@
 //
 // Per position (box o at r_n, K modes, frames of side N <= 64 kept in LDS):
 //   exit waves o P_k, 2D transform (rows then columns, each 1D pass scaled by
-//   N^-1/2: the unitary DFT of Eq. 1) of every mode, Psi_k parked in the work
-//   frames X[0][k]; the incoherent mode sum, the separable Gaussian blur of the
+//   N^-1/2: the unitary DFT of Eq. 1) of every mode, Psi_0 kept in LDS and
+//   further modes parked in the work frames X[0][k]; the incoherent mode sum, the separable Gaussian blur of the
 //   amplitude (Eq. 6) or the intensity (Eq. 2), vertical then horizontal, the
 //   modulus factor and the position's data error (box 1); per mode
 //   Psi' = f Psi_k, inverse transform, dpsi = psi' - o P_k, the object
@@ -35,9 +35,9 @@ struct SeqLds {
   using ColF = Frame<N, N, true>;
   static constexpr int ROW = RowF::ELEMS;  // float2, row-pass layout
   static constexpr int COL = ColF::ELEMS;  // float2, column-pass layout
-  // tw [N] | row buffer | column buffer | box [N^2] float2 | factor [N^2] float
+  // tw [N] | row buffer | column buffer | box [N^2] float2 | mode-0 frame [N^2] float2 | factor [N^2] float
   static constexpr size_t BYTES =
-      sizeof(float2) * ((size_t)N + ROW + COL + (size_t)N * N) + sizeof(float) * (size_t)N * N;
+      sizeof(float2) * ((size_t)N + ROW + COL + 2 * (size_t)N * N) + sizeof(float) * (size_t)N * N;
 };
 
 template <int N>
@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
   float2* rowbuf = sm + N;
   float2* colbuf = rowbuf + SeqLds<N>::ROW;
   float2* obox = colbuf + SeqLds<N>::COL;
-  float* fbuf = reinterpret_cast<float*>(obox + NN);
+  float2* psi0 = obox + NN;  // Psi of mode 0 stays on chip; further modes are parked in X
+  float* fbuf = reinterpret_cast<float*>(psi0 + NN);
   float* t0 = reinterpret_cast<float*>(rowbuf);  // blur buffers, free between the transforms
   float* t1 = reinterpret_cast<float*>(colbuf);
   for (int i = threadIdx.x; i < N; i += kThreads) tw[i] = d.tw[i];
@@ -82,14 +83,33 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
   for (int step = 0; step < np; ++step) {
     const int pat = order[step];
     const int2 rc = d.pos[pat];
-    // box into LDS (row-major) and its largest |o|^2
+    // box into LDS (row-major) and its largest |o|^2; the measured amplitudes are
+    // fetched with it (every load of the position's first round trip issued together)
     float vmax = 0.f;
-    for (int e = threadIdx.x; e < NN; e += kThreads) {
-      const int y = e / N, x = e - y * N;
-      const float2 o = d.obj[(size_t)(rc.x + y) * W + rc.y + x];
-      obox[e] = o;
-      vmax = fmaxf(vmax, o.x * o.x + o.y * o.y);
+    float av[EP];
+    {
+      const float* amp = d.amp + (size_t)pat * NN;
+      float2 ob[EP];
+#pragma unroll
+      for (int j = 0; j < EP; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (NN % kThreads != 0 && e >= NN) continue;
+        const int y = e / N, x = e - y * N;
+        ob[j] = d.obj[(size_t)(rc.x + y) * W + rc.y + x];
+        av[j] = amp[e];
+      }
+#pragma unroll
+      for (int j = 0; j < EP; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (NN % kThreads != 0 && e >= NN) continue;
+        obox[e] = ob[j];
+        vmax = fmaxf(vmax, ob[j].x * ob[j].x + ob[j].y * ob[j].y);
+      }
     }
+    // mode 0 of the probe at the forward pass's input slots and the inverse pass's output slots
+    float2 pf0[LR], pi0[SR];
+    for_load_slots<N, N, false>([&](int s, int y, int x) { pf0[s] = d.probe[y * N + x]; });
+    for_store_slots<N, N, false>([&](int s, int y, int x) { pi0[s] = d.probe[y * N + x]; });
     vmax = block_max_f(vmax, redf);  // also: the box is visible to every thread
     // forward transforms of every mode; |Psi_k|^2 summed in the column pass's store slots
     float acc[SR];
@@ -99,7 +119,9 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
       const float2* pk = d.probe + (size_t)k * NN;
       float2* xk = X + (size_t)k * NN;
       float2 v[LR];
-      auto load_row = [&](int s, int y, int x) { return cmul(obox[y * N + x], pk[y * N + x]); };
+      auto load_row = [&](int s, int y, int x) {
+        return cmul(obox[y * N + x], k == 0 ? pf0[s] : pk[y * N + x]);
+      };
       fft_gather<N, N, false>(v, load_row);
       fft_first<N, N, false, false>(v, rowbuf);
       auto to_col = [&](int s, int y, int u, float2 z) { colbuf[ColF::lidx(u, y)] = cscale(z, scale); };
@@ -108,7 +130,10 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
       auto from_col = [&](int s, int u, int y) { return colbuf[ColF::lidx(u, y)]; };
       auto park = [&](int s, int u, int y, float2 z) {
         z = cscale(z, scale);
-        xk[y * N + u] = z;
+        if (k == 0)
+          psi0[y * N + u] = z;
+        else
+          xk[y * N + u] = z;
         acc[s] += z.x * z.x + z.y * z.y;
       };
       fft_reg<N, N, true, false, true>(colbuf, tw, from_col, park);
@@ -143,7 +168,6 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
     __syncthreads();
     double err = 0.0;
     {
-      const float* amp = d.amp + (size_t)pat * NN;
       float gv[EP];
 #pragma unroll
       for (int j = 0; j < EP; ++j) {
@@ -165,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
       for (int j = 0; j < EP; ++j) {
         const int e = threadIdx.x + j * kThreads;
         if (NN % kThreads != 0 && e >= NN) continue;
-        const float a = amp[e];
+        const float a = av[j];
         float ag, f;
         if (inten) {
           ag = sqrtf(gv[j]);
@@ -192,8 +216,11 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
     for (int k = 0; k < K; ++k) {
       float2* pk = d.probe + (size_t)k * NN;
       const float2* xk = X + (size_t)k * NN;
+      // P_k at the row pass's output slots, fetched before the transforms
+      float2 pvs[SR];
+      for_store_slots<N, N, false>([&](int s, int y, int x) { pvs[s] = k == 0 ? pi0[s] : pk[y * N + x]; });
       auto load_icol = [&](int s, int u, int y) {
-        const float2 z = xk[y * N + u];
+        const float2 z = k == 0 ? psi0[y * N + u] : xk[y * N + u];
         const float f = fbuf[y * N + u];
         return make_float2(z.x * f, z.y * f);  // no contraction anywhere in this file (fft_lds.hpp)
       };
@@ -205,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
         const int e = y * N + x;
         const float2 psi_new = cscale(z, scale);
         const float2 o = obox[e];
-        const float2 pv = pk[e];
+        const float2 pv = pvs[s];
         const float2 dpsi = csub(psi_new, cmul(o, pv));
         num[s] = cadd(num[s], cmulc(dpsi, pv));
         pw[s] += pv.x * pv.x + pv.y * pv.y;
