@@ -641,7 +641,7 @@ def batched_leg(iters):
         r.close()
     dft_rows, wall_dft, wall_fft_sub, upd_sub = [], 0.0, 0.0, 0
     for (sp, s), ref in zip(cases, singles):
-        if s["n"] not in (64, 128, 256):
+        if s["n"] not in (64, 128, 192, 256):
             continue
         with make(sp, s, dft=True) as r:
             r.iterate(1)
@@ -657,7 +657,7 @@ def batched_leg(iters):
         upd_sub += len(s["positions"]) * s["k"]
     # the FP32 path on the same subset (eager launches like the DFT runs), for the comparison
     for (sp, s), r in zip(cases, singles):
-        if s["n"] in (64, 128, 256):
+        if s["n"] in (64, 128, 192, 256):
             r.set_graph(False)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -81,7 +81,7 @@ typedef struct ptycho_params {
   uint64_t seed;                 /* random sequence S_n when no explicit order is given */
   /* 1: propagate by the unitary DFT as dense complex GEMMs on BF16 matrix cores
    * with a two-term split of both operands (x = x_hi + x_lo) and FP32
-   * accumulation, instead of the FP32 FFT passes.  Far field, n in {64, 128, 256}.
+   * accumulation, instead of the FP32 FFT passes.  Far field, n in {64, 128, 192, 256}.
    * The modulus constraint, the step normalisation and the mode
    * orthogonalisation stay in FP32.  Results differ from the FP32 path by the
    * split's rounding (about 1e-5 relative per transform). */
@@ -262,7 +262,7 @@ const char* ptycho_group_last_error(const ptycho_group* g);
 
 /* The unitary 2D DFT (inverse != 0: its inverse) of `frames` device frames
  * [frames][n][n][2] in place, by the BF16-split matrix-core GEMMs of the
- * dft_bf16 path (n in {64, 128, 256}), ordered on hip_stream (NULL = null stream);
+ * dft_bf16 path (n in {64, 128, 192, 256}), ordered on hip_stream (NULL = null stream);
  * synchronises it.  For measuring that path's error and speed on its own. */
 ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, int32_t inverse, void* hip_stream);
 

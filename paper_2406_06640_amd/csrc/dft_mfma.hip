@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_delta(const CaseDesc* __restri
 // Launchers
 // ---------------------------------------------------------------------------
 
-bool dft_supported(int n) { return n == 64 || n == 128 || n == 256; }
+bool dft_supported(int n) { return n == 64 || n == 128 || n == 192 || n == 256; }
 int dft_err_slots(int n) { return (n / kDftTile) * (n / kDftTile); }
 
 template <int N>
@@ -367,6 +367,7 @@ hipError_t launch_dft2(float2* X, const void* planes, int n, int frames, bool in
   switch (n) {
     case 64: return dft2_t<64>(X, pl, frames, inverse, s);
     case 128: return dft2_t<128>(X, pl, frames, inverse, s);
+    case 192: return dft2_t<192>(X, pl, frames, inverse, s);  // 3 tiles of 16 per wave, 6 k-chunks of 32
     case 256: return dft2_t<256>(X, pl, frames, inverse, s);
     default: return hipErrorInvalidValue;
   }

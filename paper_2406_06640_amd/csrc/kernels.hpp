@@ -165,7 +165,7 @@ int dm_segments(int n_pos, int seg_len);
 bool seq_supported(int n, bool near_field);
 hipError_t launch_seq_iter(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
 
-// BF16 matrix-core DFT path (far field, n in {64, 128, 256}); single table only.
+// BF16 matrix-core DFT path (far field, n in {64, 128, 192, 256}); single table only.
 // planes: [4][n][n] bf16 (re_hi, re_lo, im_hi, im_lo) of F[u][x] = exp(-2 pi i u x / n) / sqrt(n).
 bool dft_supported(int n);
 int dft_err_slots(int n);

@@ -160,7 +160,7 @@ std::string validate(const ptycho_params* p) {
   if (p->orthogonalize != 0 && p->orthogonalize != 1) return "orthogonalize must be 0 or 1";
   if (p->dft_bf16 != 0 && p->dft_bf16 != 1) return "dft_bf16 must be 0 or 1";
   if (p->dft_bf16 && (p->geometry != PTYCHO_FAR_FIELD || !dft_supported(p->n)))
-    return "dft_bf16 needs the far field and n in {64, 128, 256}";
+    return "dft_bf16 needs the far field and n in {64, 128, 192, 256}";
   if (p->engine != PTYCHO_ENGINE_EPIE && p->engine != PTYCHO_ENGINE_DM) return "bad engine";
   if (p->engine == PTYCHO_ENGINE_DM) {
     if (!(finite_f(p->dm_reg) && p->dm_reg > 0)) return "dm_reg must be finite and > 0";
@@ -1733,7 +1733,7 @@ void ptycho_group_destroy(ptycho_group* g) {
 
 ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, int32_t inverse, void* hip_stream) {
   if (!frames_inout || frames < 0 || !dft_supported(n))
-    return fail(nullptr, PTYCHO_E_INVALID, "need device frames and n in {64, 128, 256}");
+    return fail(nullptr, PTYCHO_E_INVALID, "need device frames and n in {64, 128, 192, 256}");
   if (frames == 0) return PTYCHO_OK;
   static std::mutex mu;
   static std::map<std::pair<int, int>, void*> cache;  // (device, n) -> planes; kept for the process

@@ -2,7 +2,7 @@
 
 Case i (N in {64, 128, 192, 256}, 1-8 modes, seeds [1004, i]) is built from its
 first 32 raster positions; one batch step of those 32 positions from the plain
-start runs through the FP32 FFT path and, for N in {64, 128, 256}, through the
+start runs through the FP32 FFT path and through the
 BF16 matrix-core DFT path, and the oracle takes the same step in FP64.  The
 relative L2 errors of psi', the modulus factor, the object and probe numerators
 and the updated object and probe are printed per case ("[c4-oracle]" lines) and
@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 FP32_TOL = 1e-5
 FP32_FACTOR_TOL = 1e-4
 BF16_TOL = 1e-3
-BF16_SIZES = (64, 128, 256)
+BF16_SIZES = (64, 128, 192, 256)
 B = 32
 
 

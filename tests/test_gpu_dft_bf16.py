@@ -20,7 +20,7 @@ TRANSFORM_TOL = 1e-4
 STEP_TOL = 1e-3
 
 
-@pytest.mark.parametrize("n", [64, 128, 256])
+@pytest.mark.parametrize("n", [64, 128, 192, 256])
 def test_dft2_bf16_matches_exact_dft(n):
     import torch
     import paper_2406_06640_amd as P
@@ -38,7 +38,7 @@ def test_dft2_bf16_matches_exact_dft(n):
     assert fwd < TRANSFORM_TOL and back < 2 * TRANSFORM_TOL
 
 
-@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("n", [64, 128, 192])
 def test_dft_bf16_batch_step_error(n):
     s = make_case(n=n, k=2, obj=(n + 48, n + 48), n_side=4, step=12, radius=n // 4, seed=40 + n)
     cp, op = params_pair(s, batch=4, cc_start=1, cc_end=2)
