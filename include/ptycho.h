@@ -266,6 +266,35 @@ const char* ptycho_group_last_error(const ptycho_group* g);
  * synchronises it.  For measuring that path's error and speed on its own. */
 ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, int32_t inverse, void* hip_stream);
 
+/* Numerical monochromatisation of broadband far-field patterns (Sec. 4.2):
+ * the broadband pattern is modelled as b = C m, and the monochromatic pattern m
+ * is estimated by k iterations of CGLS from x_0 = 0, the k-th iterate being the
+ * least-squares solution of ||C x - b|| over the Krylov subspace
+ * span{C^T b, (C^T C) C^T b, ..., (C^T C)^(k-1) C^T b} (Eq. 12-13; the paper uses
+ * k up to 40, k = 25 typically).  C depends only on the spectrum: on a fixed
+ * detector the pattern at wavelength lambda_j is m magnified about the centre
+ * pixel (n/2, n/2) by s_j = lambda_c / lambda_j and weighted by w_j s_j^2
+ * (sum w_j = 1, so each wavelength carries its weight's power), sampled
+ * bilinearly with zero outside the frame; C^T is its exact adjoint.
+ *  create: n even in [2, 4096]; max_patterns >= 1; scales[n_lambda] > 0 and
+ *          weights[n_lambda] >= 0 (normalised here), host arrays, n_lambda in
+ *          [1, 16]; hip_stream orders every call (NULL = null stream).  Owns
+ *          5 x max_patterns x n^2 floats of device work and staging memory.
+ *  run:    broadband [n_patterns][n][n] float (zero frequency at (n/2, n/2)) into
+ *          mono_out [n_patterns][n][n] (host or device per mem_kind; may not
+ *          alias); residuals (host, may be NULL) [n_patterns][k_iters + 1] gets
+ *          ||C x_i - b|| for i = 0 .. k_iters.  Patterns are independent and run
+ *          together.  Synchronises the stream.  The output can be negative where
+ *          the data are noisy; ptycho_init clamps intensities at zero.
+ * Errors: PTYCHO_E_INVALID, PTYCHO_E_SHAPE, PTYCHO_E_OOM, PTYCHO_E_HIP; the text is
+ * in ptycho_last_error(NULL). */
+typedef struct ptycho_mono ptycho_mono;
+ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* scales, const float* weights,
+                                 int32_t n_lambda, void* hip_stream, ptycho_mono** out);
+ptycho_status ptycho_mono_run(ptycho_mono* m, const float* broadband, float* mono_out, int32_t n_patterns,
+                              int32_t k_iters, float* residuals, int32_t mem_kind);
+void ptycho_mono_destroy(ptycho_mono* m);
+
 /* Host-only: the order used for iteration t when none is given -- Fisher-Yates
  * over 0..n_pos-1 (for i = n_pos-1 .. 1: j = next % (i + 1), swap) with `next`
  * the SplitMix64 sequence (Steele, Lea, Flood 2014) seeded with seed XOR t.

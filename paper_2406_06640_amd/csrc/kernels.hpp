@@ -165,6 +165,25 @@ int dm_segments(int n_pos, int seg_len);
 bool seq_supported(int n, bool near_field);
 hipError_t launch_seq_iter(const CaseDesc* cases, const TableShape& t, const int* it, hipStream_t s);
 
+// Numerical monochromatisation by CGLS: spectrum (scales s_j = lambda_c / lambda_j
+// and coefficients w_j s_j^2 with sum w_j = 1) and the work buffers of n_pat patterns.
+constexpr int kMonoMaxLambda = 16;
+struct MonoSpectrum {
+  int count;
+  float scale[kMonoMaxLambda];
+  float coef[kMonoMaxLambda];
+};
+struct MonoWork {
+  MonoSpectrum spec;
+  float *r, *s, *p, *q;   // [n_pat][n][n] CGLS vectors
+  double *part, *part2;   // [n_pat][blocks] partial sums
+  double *gamma, *coef;   // [n_pat] |C^T r|^2 and alpha / beta
+};
+// k_iters CGLS iterations from x = 0 for every pattern of b into x; res (device,
+// [n_pat][k_iters + 1], may be null) receives |C x_i - b| for i = 0 .. k_iters.
+hipError_t launch_mono_cgls(const float* b, float* x, const MonoWork& w, int n, int n_pat, int k_iters, float* res,
+                            hipStream_t s);
+
 // BF16 matrix-core DFT path (far field, n in {64, 128, 192, 256}); single table only.
 // planes: [4][n][n] bf16 (re_hi, re_lo, im_hi, im_lo) of F[u][x] = exp(-2 pi i u x / n) / sqrt(n).
 bool dft_supported(int n);

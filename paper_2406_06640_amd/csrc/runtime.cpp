@@ -82,6 +82,16 @@ struct ptycho_ctx {
   Timing tm;
 };
 
+struct ptycho_mono {
+  int n = 0, max_pat = 0;
+  MonoWork w{};
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  float *d_in = nullptr, *d_out = nullptr;  // staging of host patterns
+  float* d_res = nullptr;                   // residual history
+  size_t res_cap = 0;
+};
+
 struct ptycho_group {
   std::vector<ptycho_ctx*> ctx;
   struct Table {
@@ -1761,6 +1771,92 @@ ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, i
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(nullptr, PTYCHO_E_HIP, std::string("dft2_bf16: ") + hipGetErrorString(e));
   return PTYCHO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Numerical monochromatisation by CGLS (Sec. 4.2)
+// ---------------------------------------------------------------------------
+
+ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* scales, const float* weights,
+                                 int32_t n_lambda, void* hip_stream, ptycho_mono** out) {
+  if (out) *out = nullptr;
+  if (!out || !scales || !weights) return fail(nullptr, PTYCHO_E_INVALID, "NULL argument");
+  if (n < 2 || n > 4096 || (n & 1)) return fail(nullptr, PTYCHO_E_SHAPE, "n must be even and in [2, 4096]");
+  if (max_patterns < 1) return fail(nullptr, PTYCHO_E_SHAPE, "max_patterns must be >= 1");
+  if (n_lambda < 1 || n_lambda > kMonoMaxLambda) return fail(nullptr, PTYCHO_E_INVALID, "n_lambda must be in [1, 16]");
+  double wsum = 0.0;
+  for (int j = 0; j < n_lambda; ++j) {
+    if (!(std::isfinite(scales[j]) && scales[j] > 0.f)) return fail(nullptr, PTYCHO_E_INVALID, "scales must be > 0");
+    if (!(std::isfinite(weights[j]) && weights[j] >= 0.f)) return fail(nullptr, PTYCHO_E_INVALID, "weights must be >= 0");
+    wsum += weights[j];
+  }
+  if (!(wsum > 0.0)) return fail(nullptr, PTYCHO_E_INVALID, "the weights must not all be zero");
+  ptycho_mono* m = new ptycho_mono();
+  m->n = n;
+  m->max_pat = max_patterns;
+  m->stream = (hipStream_t)hip_stream;
+  m->w.spec.count = n_lambda;
+  for (int j = 0; j < n_lambda; ++j) {
+    m->w.spec.scale[j] = scales[j];
+    m->w.spec.coef[j] = (float)(weights[j] / wsum * (double)scales[j] * (double)scales[j]);
+  }
+  const size_t nn = (size_t)n * n, tot = nn * max_patterns;
+  const size_t blocks = (nn + 255) / 256;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) return false;
+    m->allocs.push_back(*p);
+    return true;
+  };
+  if (!alloc((void**)&m->w.r, tot * 4) || !alloc((void**)&m->w.s, tot * 4) || !alloc((void**)&m->w.p, tot * 4) ||
+      !alloc((void**)&m->w.q, tot * 4) || !alloc((void**)&m->w.part, blocks * max_patterns * 8) ||
+      !alloc((void**)&m->w.part2, blocks * max_patterns * 8) || !alloc((void**)&m->w.gamma, max_patterns * 8) ||
+      !alloc((void**)&m->w.coef, max_patterns * 8) || !alloc((void**)&m->d_in, tot * 4) ||
+      !alloc((void**)&m->d_out, tot * 4)) {
+    ptycho_mono_destroy(m);
+    return fail(nullptr, PTYCHO_E_OOM, "device allocation failed");
+  }
+  *out = m;
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_mono_run(ptycho_mono* m, const float* broadband, float* mono_out, int32_t n_patterns,
+                              int32_t k_iters, float* residuals, int32_t mem_kind) {
+  if (!m || !broadband || !mono_out) return fail(nullptr, PTYCHO_E_INVALID, "NULL argument");
+  if (n_patterns < 1 || n_patterns > m->max_pat) return fail(nullptr, PTYCHO_E_SHAPE, "n_patterns must be in [1, max_patterns]");
+  if (k_iters < 0 || k_iters > 100000) return fail(nullptr, PTYCHO_E_INVALID, "k_iters must be in [0, 100000]");
+  if (mem_kind != PTYCHO_MEM_HOST && mem_kind != PTYCHO_MEM_DEVICE) return fail(nullptr, PTYCHO_E_INVALID, "bad mem_kind");
+  const size_t bytes = (size_t)m->n * m->n * n_patterns * sizeof(float);
+  hipStream_t s = m->stream;
+  const float* b = broadband;
+  float* x = mono_out;
+  if (mem_kind == PTYCHO_MEM_HOST) {
+    if (hipMemcpyAsync(m->d_in, broadband, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(nullptr, PTYCHO_E_HIP, "upload failed");
+    b = m->d_in;
+    x = m->d_out;
+  }
+  const size_t nres = (size_t)n_patterns * (k_iters + 1);
+  if (residuals && nres > m->res_cap) {
+    if (m->d_res) (void)hipFree(m->d_res);
+    m->d_res = nullptr;
+    m->res_cap = 0;
+    if (hipMalloc((void**)&m->d_res, nres * sizeof(float)) != hipSuccess) return fail(nullptr, PTYCHO_E_OOM, "residual buffer");
+    m->res_cap = nres;
+  }
+  hipError_t e = launch_mono_cgls(b, x, m->w, m->n, n_patterns, k_iters, residuals ? m->d_res : nullptr, s);
+  if (e == hipSuccess && mem_kind == PTYCHO_MEM_HOST) e = hipMemcpyAsync(mono_out, x, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && residuals) e = hipMemcpyAsync(residuals, m->d_res, nres * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(nullptr, PTYCHO_E_HIP, std::string("monochromatisation: ") + hipGetErrorString(e));
+  return PTYCHO_OK;
+}
+
+void ptycho_mono_destroy(ptycho_mono* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->stream);
+  for (void* p : m->allocs) (void)hipFree(p);
+  if (m->d_res) (void)hipFree(m->d_res);
+  delete m;
 }
 
 const char* ptycho_group_last_error(const ptycho_group* g) { return g ? g->err.c_str() : g_thread_error.c_str(); }

@@ -22,6 +22,7 @@ __all__ = [
     "PTYCHO_E_NUMERIC", "PTYCHO_E_STATE", "PTYCHO_FAR_FIELD", "PTYCHO_NEAR_FIELD",
     "PTYCHO_BLUR_AMPLITUDE", "PTYCHO_BLUR_INTENSITY", "PTYCHO_MEM_HOST", "PTYCHO_MEM_DEVICE",
     "PTYCHO_ENGINE_EPIE", "PTYCHO_ENGINE_DM", "ptycho_get_exit_waves", "ptycho_set_exit_waves",
+    "ptycho_mono_create", "ptycho_mono_run", "ptycho_mono_destroy", "Monochromatiser",
     "PtychoParams", "PtychoError", "lib", "library_path", "load_library", "default_params",
     "ptycho_init", "ptycho_iterate", "ptycho_iterate_static", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
     "ptycho_iteration", "ptycho_debug_step", "ptycho_destroy", "ptycho_last_error",
@@ -90,6 +91,9 @@ def load_library():
         "ptycho_iterate": (i32, [vp, i32, fp, fp]),
         "ptycho_iterate_static": (i32, [vp, i32, fp, fp]),
         "ptycho_get_exit_waves": (i32, [vp, fp, i32]),
+        "ptycho_mono_create": (i32, [i32, i32, fp, fp, i32, vp, P(vp)]),
+        "ptycho_mono_run": (i32, [vp, fp, fp, i32, i32, fp, i32]),
+        "ptycho_mono_destroy": (None, [vp]),
         "ptycho_set_exit_waves": (i32, [vp, fp, i32]),
         "ptycho_get_object": (i32, [vp, fp, i32]),
         "ptycho_get_probe": (i32, [vp, fp, i32]),
@@ -453,6 +457,67 @@ class Reconstruction:
         if self.ctx:
             ptycho_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# Numerical monochromatisation by CGLS (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+def ptycho_mono_create(n, max_patterns, scales, weights, stream=None):
+    sc = np.ascontiguousarray(scales, dtype=np.float32)
+    wt = np.ascontiguousarray(weights, dtype=np.float32)
+    if sc.shape != wt.shape or sc.ndim != 1:
+        raise ValueError("scales and weights must be 1D arrays of one length")
+    out = ctypes.c_void_p()
+    st = load_library().ptycho_mono_create(int(n), int(max_patterns), ctypes.c_void_p(sc.ctypes.data),
+                                           ctypes.c_void_p(wt.ctypes.data), int(sc.size), _stream_handle(stream),
+                                           ctypes.byref(out))
+    _check(st, None)
+    return out
+
+
+def ptycho_mono_run(handle, broadband, out, k_iters, residuals=True):
+    """broadband / out: numpy float32 [P][n][n] (host) or CUDA tensors (device).  Returns the
+    residual history [P][k_iters + 1] (numpy) or None."""
+    mk = PTYCHO_MEM_DEVICE if _is_torch(broadband) else PTYCHO_MEM_HOST
+    keep = []
+    n_pat = int(broadband.shape[0])
+    res = np.zeros((n_pat, int(k_iters) + 1), dtype=np.float32) if residuals else None
+    st = load_library().ptycho_mono_run(handle, _ptr(broadband, np.float32, mk, keep), _out_ptr(out, mk), n_pat,
+                                        int(k_iters), ctypes.c_void_p(res.ctypes.data) if residuals else None, mk)
+    _check(st, None)
+    return res
+
+
+def ptycho_mono_destroy(handle):
+    load_library().ptycho_mono_destroy(handle)
+
+
+class Monochromatiser:
+    """Owning wrapper of a monochromatisation plan (ptycho_mono_*)."""
+
+    def __init__(self, n, max_patterns, scales, weights, stream=None):
+        self.handle = ptycho_mono_create(n, max_patterns, scales, weights, stream)
+
+    def run(self, broadband, out, k_iters, residuals=True):
+        return ptycho_mono_run(self.handle, broadband, out, k_iters, residuals)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ptycho_mono_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:
