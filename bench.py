@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 PMC_PROFILE = os.path.join(ROOT, "profiles", "far256_k4_b32_pmc_traffic.txt")
-KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "fft_lds.hpp", "dft_mfma.hip"]
+KERNEL_SOURCES = ["kernels.hip", "kernels.hpp", "kernels_dev.hpp", "fft_lds.hpp", "dft_mfma.hip"]
 
 
 def measured_traffic(kernel_class):
