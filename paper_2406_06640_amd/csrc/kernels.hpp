@@ -168,17 +168,33 @@ hipError_t launch_seq_iter(const CaseDesc* cases, const TableShape& t, const int
 // Numerical monochromatisation by CGLS: spectrum (scales s_j = lambda_c / lambda_j
 // and coefficients w_j s_j^2 with sum w_j = 1) and the work buffers of n_pat patterns.
 constexpr int kMonoMaxLambda = 16;
+constexpr float kMonoMinScale = 1.0f / 16.0f, kMonoMaxScale = 16.0f;
 struct MonoSpectrum {
   int count;
   float scale[kMonoMaxLambda];
   float coef[kMonoMaxLambda];
 };
+// Per-wavelength interpolation tables, built once per plan by launch_mono_tables.
+// Forward: detector pixel u samples nodes i0 and i0 + 1 with weights 1 - t and t.
+// Adjoint: node v receives from the adj_cnt consecutive pixels starting at adj_first
+// (weights adj_w, row stride adj_stride, zero where a pixel of the run does not touch v).
+struct MonoTables {
+  int* i0;        // [count][n]
+  float* t;       // [count][n]
+  int* adj_first; // [count][n]
+  int* adj_cnt;   // [count][n] run length up to the last nonzero weight
+  float* adj_w;   // [count][n][adj_stride]
+  int adj_stride; // floor(2 / min scale) + 3
+};
+int mono_adj_stride(const MonoSpectrum& sp);
 struct MonoWork {
   MonoSpectrum spec;
+  MonoTables tab;
   float *r, *s, *p, *q;   // [n_pat][n][n] CGLS vectors
   double *part, *part2;   // [n_pat][blocks] partial sums
   double *gamma, *coef;   // [n_pat] |C^T r|^2 and alpha / beta
 };
+hipError_t launch_mono_tables(const MonoWork& w, int n, hipStream_t s);
 // k_iters CGLS iterations from x = 0 for every pattern of b into x; res (device,
 // [n_pat][k_iters + 1], may be null) receives |C x_i - b| for i = 0 .. k_iters.
 hipError_t launch_mono_cgls(const float* b, float* x, const MonoWork& w, int n, int n_pat, int k_iters, float* res,

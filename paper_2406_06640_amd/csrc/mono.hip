@@ -27,56 +27,89 @@ __device__ __forceinline__ void mono_sample(int u, float c, float s, int& i0, fl
   t = p - f;
 }
 
-// Weight of node v in the sample of pixel u at scale s (the entry S[u][v] of the interpolation matrix).
-__device__ __forceinline__ float mono_weight(int u, int v, float c, float s) {
+// Forward table: i0 and t of every detector pixel at every scale.
+__global__ __launch_bounds__(kThreads) void k_mono_fwd_table(MonoSpectrum sp, MonoTables tb, int n) {
+  const int j = blockIdx.y;
+  const int u = blockIdx.x * kThreads + threadIdx.x;
+  if (u >= n) return;
   int i0;
   float t;
-  mono_sample(u, c, s, i0, t);
-  if (v == i0) return 1.0f - t;
-  if (v == i0 + 1 && t > 0.f) return t;
-  return 0.f;
+  mono_sample(u, 0.5f * (float)n, sp.scale[j], i0, t);
+  tb.i0[j * n + u] = i0;
+  tb.t[j * n + u] = t;
+}
+
+// Adjoint table from the forward table: node v takes weight 1 - t from pixels with
+// i0 = v and t from pixels with i0 = v - 1 (t > 0).  i0 is nondecreasing in u, so
+// these pixels are consecutive; the run starts at the first of them and holds
+// adj_stride weights (zero past the last).  Pixels sampling v lie where
+// v - 1 <= c + s (u - c) < v + 1, a window of width 2 / s, searched widened by one.
+__global__ __launch_bounds__(kThreads) void k_mono_adj_table(MonoSpectrum sp, MonoTables tb, int n) {
+  const int j = blockIdx.y;
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v >= n) return;
+  const float c = 0.5f * (float)n, s = sp.scale[j];
+  const int lo = max((int)floorf(((float)v - 1.0f - c) / s + c) - 1, 0);
+  const int hi = min((int)ceilf(((float)v + 1.0f - c) / s + c) + 1, n - 1);
+  const int* i0 = tb.i0 + j * n;
+  const float* tt = tb.t + j * n;
+  auto weight = [&](int u) -> float {
+    if (u < 0 || u >= n) return 0.f;
+    if (i0[u] == v) return 1.0f - tt[u];
+    if (i0[u] == v - 1 && tt[u] > 0.f) return tt[u];
+    return 0.f;
+  };
+  int first = lo;
+  while (first <= hi && weight(first) == 0.f) ++first;
+  float* w = tb.adj_w + ((size_t)j * n + v) * tb.adj_stride;
+  int cnt = 0;
+  for (int k = 0; k < tb.adj_stride; ++k) {
+    w[k] = (first <= hi) ? weight(first + k) : 0.f;
+    if (w[k] != 0.f) cnt = k + 1;
+  }
+  tb.adj_first[j * n + v] = first;
+  tb.adj_cnt[j * n + v] = cnt;
 }
 
 // out = C in (ADJ false) or C^T in (ADJ true) for every pattern; part[pattern][block] = sum out^2.
+// The adjoint sums, for each wavelength, its row weights in ascending pixel order, each
+// row's column weights in ascending order (zero weights skipped).
 template <bool ADJ>
 __global__ __launch_bounds__(kThreads) void k_mono_apply(const float* __restrict__ in, float* __restrict__ out,
-                                                         MonoSpectrum sp, int n, double* __restrict__ part) {
+                                                         MonoSpectrum sp, MonoTables tb, int n,
+                                                         double* __restrict__ part) {
   __shared__ double red[kThreads / 64];
   const size_t nn = (size_t)n * n;
   const int pat = blockIdx.y;
   const int e = blockIdx.x * kThreads + threadIdx.x;
   const float* m = in + (size_t)pat * nn;
-  const float c = 0.5f * (float)n;
   float val = 0.f;
   if (e < n * n) {
     const int uy = e / n, ux = e - uy * n;
     for (int j = 0; j < sp.count; ++j) {
-      const float s = sp.scale[j];
       float acc = 0.f;
       if (!ADJ) {
-        int iy, ix;
-        float ty, tx;
-        mono_sample(uy, c, s, iy, ty);
-        mono_sample(ux, c, s, ix, tx);
+        const int iy = tb.i0[j * n + uy], ix = tb.i0[j * n + ux];
+        const float ty = tb.t[j * n + uy], tx = tb.t[j * n + ux];
         const float r0 = (1.0f - tx) * mono_at(m, n, iy, ix) + tx * mono_at(m, n, iy, ix + 1);
         const float r1 = (1.0f - tx) * mono_at(m, n, iy + 1, ix) + tx * mono_at(m, n, iy + 1, ix + 1);
         acc = (1.0f - ty) * r0 + ty * r1;
       } else {
-        // pixels u whose sample p(u) = c + s (u - c) lies within one pixel of v: u in
-        // ((v - 1 - c) / s + c, (v + 1 - c) / s + c), widened by one for rounding
-        const int ylo = (int)floorf(((float)uy - 1.0f - c) / s + c) - 1;
-        const int yhi = (int)ceilf(((float)uy + 1.0f - c) / s + c) + 1;
-        const int xlo = (int)floorf(((float)ux - 1.0f - c) / s + c) - 1;
-        const int xhi = (int)ceilf(((float)ux + 1.0f - c) / s + c) + 1;
-        for (int a = max(ylo, 0); a <= min(yhi, n - 1); ++a) {
-          const float wy = mono_weight(a, uy, c, s);
-          if (wy == 0.f) continue;
+        const int st = tb.adj_stride;
+        const int ay = tb.adj_first[j * n + uy], ax = tb.adj_first[j * n + ux];
+        const int cy = tb.adj_cnt[j * n + uy], cx = tb.adj_cnt[j * n + ux];
+        const float* wy = tb.adj_w + ((size_t)j * n + uy) * st;
+        const float* wx = tb.adj_w + ((size_t)j * n + ux) * st;
+        for (int a = 0; a < cy; ++a) {
+          const float wa = wy[a];
+          if (wa == 0.f) continue;
+          const float* mr = m + (size_t)(ay + a) * n + ax;
           float row = 0.f;
-          for (int b = max(xlo, 0); b <= min(xhi, n - 1); ++b) {
-            const float wx = mono_weight(b, ux, c, s);
-            if (wx != 0.f) row += wx * m[a * n + b];
+          for (int b = 0; b < cx; ++b) {
+            const float wb = wx[b];
+            if (wb != 0.f) row += wb * mr[b];
           }
-          acc += wy * row;
+          acc += wa * row;
         }
       }
       val += sp.coef[j] * acc;
@@ -174,22 +207,35 @@ hipError_t launch_mono_cgls(const float* b, float* x, const MonoWork& w, int n, 
   const dim3 grid(blocks, n_pat);
   const int rs = k_iters + 1;
   pty_launch(k_mono_start, grid, dim3(kThreads), 0, s, b, x, w.r, w.p, nn, w.part2, w.gamma);
-  pty_launch(k_mono_apply<true>, grid, dim3(kThreads), 0, s, (const float*)w.r, w.s, w.spec, n, w.part);
+  pty_launch(k_mono_apply<true>, grid, dim3(kThreads), 0, s, (const float*)w.r, w.s, w.spec, w.tab, n, w.part);
   pty_launch(k_mono_scalar, dim3(n_pat), dim3(64), 0, s, (const double*)w.part, (const double*)w.part2, blocks, 1,
              w.gamma, w.coef, res, 0, rs);
   // the start's beta is 0 (gamma was 0): p = s
   pty_launch(k_mono_p, grid, dim3(kThreads), 0, s, w.p, (const float*)w.s, (const double*)w.coef, nn);
   for (int k = 0; k < k_iters; ++k) {
-    pty_launch(k_mono_apply<false>, grid, dim3(kThreads), 0, s, (const float*)w.p, w.q, w.spec, n, w.part);
+    pty_launch(k_mono_apply<false>, grid, dim3(kThreads), 0, s, (const float*)w.p, w.q, w.spec, w.tab, n, w.part);
     pty_launch(k_mono_scalar, dim3(n_pat), dim3(64), 0, s, (const double*)w.part, (const double*)nullptr, blocks,
                0, w.gamma, w.coef, (float*)nullptr, 0, rs);
     pty_launch(k_mono_xr, grid, dim3(kThreads), 0, s, x, w.r, (const float*)w.p, (const float*)w.q,
                (const double*)w.coef, nn, w.part2);
-    pty_launch(k_mono_apply<true>, grid, dim3(kThreads), 0, s, (const float*)w.r, w.s, w.spec, n, w.part);
+    pty_launch(k_mono_apply<true>, grid, dim3(kThreads), 0, s, (const float*)w.r, w.s, w.spec, w.tab, n, w.part);
     pty_launch(k_mono_scalar, dim3(n_pat), dim3(64), 0, s, (const double*)w.part, (const double*)w.part2, blocks,
                1, w.gamma, w.coef, res, k + 1, rs);
     pty_launch(k_mono_p, grid, dim3(kThreads), 0, s, w.p, (const float*)w.s, (const double*)w.coef, nn);
   }
+  return hipGetLastError();
+}
+
+int mono_adj_stride(const MonoSpectrum& sp) {
+  float smin = sp.scale[0];
+  for (int j = 1; j < sp.count; ++j) smin = fminf(smin, sp.scale[j]);
+  return (int)floorf(2.0f / smin) + 3;
+}
+
+hipError_t launch_mono_tables(const MonoWork& w, int n, hipStream_t s) {
+  const dim3 grid((n + kThreads - 1) / kThreads, w.spec.count);
+  pty_launch(k_mono_fwd_table, grid, dim3(kThreads), 0, s, w.spec, w.tab, n);
+  pty_launch(k_mono_adj_table, grid, dim3(kThreads), 0, s, w.spec, w.tab, n);
   return hipGetLastError();
 }
 

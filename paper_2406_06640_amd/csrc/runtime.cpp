@@ -1786,7 +1786,8 @@ ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* s
   if (n_lambda < 1 || n_lambda > kMonoMaxLambda) return fail(nullptr, PTYCHO_E_INVALID, "n_lambda must be in [1, 16]");
   double wsum = 0.0;
   for (int j = 0; j < n_lambda; ++j) {
-    if (!(std::isfinite(scales[j]) && scales[j] > 0.f)) return fail(nullptr, PTYCHO_E_INVALID, "scales must be > 0");
+    if (!(std::isfinite(scales[j]) && scales[j] >= kMonoMinScale && scales[j] <= kMonoMaxScale))
+      return fail(nullptr, PTYCHO_E_INVALID, "scales must be in [1/16, 16]");
     if (!(std::isfinite(weights[j]) && weights[j] >= 0.f)) return fail(nullptr, PTYCHO_E_INVALID, "weights must be >= 0");
     wsum += weights[j];
   }
@@ -1814,6 +1815,21 @@ ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* s
       !alloc((void**)&m->d_out, tot * 4)) {
     ptycho_mono_destroy(m);
     return fail(nullptr, PTYCHO_E_OOM, "device allocation failed");
+  }
+  MonoTables& tb = m->w.tab;
+  tb.adj_stride = mono_adj_stride(m->w.spec);
+  const size_t tn = (size_t)n_lambda * n;
+  if (!alloc((void**)&tb.i0, tn * 4) || !alloc((void**)&tb.t, tn * 4) || !alloc((void**)&tb.adj_first, tn * 4) ||
+      !alloc((void**)&tb.adj_cnt, tn * 4) ||
+      !alloc((void**)&tb.adj_w, tn * tb.adj_stride * 4)) {
+    ptycho_mono_destroy(m);
+    return fail(nullptr, PTYCHO_E_OOM, "device allocation failed");
+  }
+  hipError_t e = launch_mono_tables(m->w, n, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) {
+    ptycho_mono_destroy(m);
+    return fail(nullptr, PTYCHO_E_HIP, std::string("monochromatisation tables: ") + hipGetErrorString(e));
   }
   *out = m;
   return PTYCHO_OK;

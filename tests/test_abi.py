@@ -152,3 +152,24 @@ def test_forward_model_config_validation(field, value, status):
     h = ctypes.c_void_p()
     assert lib.ptycho_fm_create(ctypes.byref(cfg), 4, None, ctypes.byref(h)) == status
     assert not h.value
+
+
+@pytest.mark.parametrize("n,count,scales,weights,status", [
+    (31, 4, [1.0], [1.0], -2),                     # n odd
+    (32, 0, [1.0], [1.0], -2),                     # no patterns
+    (32, 4, [1.0, 0.05], [1.0, 1.0], -1),          # scale below 1/16
+    (32, 4, [20.0], [1.0], -1),                    # scale above 16
+    (32, 4, [1.0, 1.1], [0.0, 0.0], -1),           # all weights zero
+    (32, 4, [1.0, 1.1], [1.0, -0.5], -1),          # negative weight
+])
+def test_monochromatiser_rejects_bad_plans_without_device_work(n, count, scales, weights, status):
+    """ptycho_mono_create validates its host arguments before any HIP call."""
+    import ctypes
+    import paper_2406_06640_amd as P
+    lib = P.load_library()
+    h = ctypes.c_void_p()
+    sc = (ctypes.c_float * len(scales))(*scales)
+    wt = (ctypes.c_float * len(weights))(*weights)
+    assert lib.ptycho_mono_create(n, count, sc, wt, len(scales), None, ctypes.byref(h)) == status
+    assert not h.value
+    assert P.ptycho_last_error(None)
