@@ -21,6 +21,12 @@ for B > 1 beyond those properties.
 2, Sec. 4.5), pinned by the least-squares property of its overlap projection,
 the consistent-data fixed point, the single-position reduction to the Fourier
 modulus projection and noise-free convergence (``tests/test_oracle_dm.py``).
+
+``oracle.pclsqml`` is the FP64 pc-LSQML engine (LSQML of ref. [27] with boxes 1
+and 2, Sec. 3.2 and 4.1), pinned by library least squares on its step pair
+(undamped and damped), the consistent-data fixed point, the single-position
+landing on the modulus projection, the closed-form steps of one position and
+noise-free convergence (``tests/test_oracle_lsqml.py``).
 """
 
 from .pcepie import *  # noqa: F401,F403
