@@ -454,6 +454,55 @@ def dm_leg(P, torch, s, spec, iters, copy_gbs, batch=32):
             "final_data_error": float(errs[-1])}
 
 
+def lsqml_leg(P, torch, s, spec, iters, copy_gbs, batch=32, lam=0.1):
+    """The pc-LSQML engine (LSQML of ref. [27] with boxes 1 and 2, Sec. 3.2 and 4.1) on the
+    headline workload, batch by batch as pc-ePIE.  Pass model: pc-ePIE's, plus per position the
+    step normal equations' read of the K exit-wave updates, the box and the object direction
+    (8 K N^2 + 16 N^2 bytes, (16 K + 40) N^2 flop), plus per batch the object direction written
+    over the union of its boxes (8 |union|) and the probe direction written and read (16 K N^2)."""
+    dev = torch.device("cuda:0")
+    n, k, n_pos = s["n"], s["k"], len(s["positions"])
+    cp = make_params(P, s, spec, batch)
+    cp.engine = P.PTYCHO_ENGINE_LSQML
+    cp.lsq_damping = lam
+    cp.gamma_obj = cp.gamma_probe = 0.1
+    inten = torch.from_numpy(s["intensities"]).to(dev)
+    pos = torch.from_numpy(s["positions"]).to(dev)
+    probe0 = torch.from_numpy(s["probe0"].astype(np.complex64)).to(dev)
+    obj0 = torch.from_numpy(s["obj0"].astype(np.complex64)).to(dev)
+    names = P.kernel_names()
+    with P.Reconstruction(cp, inten, pos, probe0, obj0, mem_kind=P.PTYCHO_MEM_DEVICE) as r:
+        r.iterate(1)
+        P.ptycho_set_timing(r.ctx, (1 << len(names)) - 1)
+        r.iterate(1)
+        P.ptycho_set_timing(r.ctx, 0)
+        prof = {nm: P.ptycho_kernel_time(r.ctx, i, reset=True) for i, nm in enumerate(names)}
+        r.set_graph(True)
+        r.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs = r.iterate(iters)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        mean = r.lsq_steps()[1]
+    ms = 1e3 * wall / iters
+    nn = n * n
+    order = P.ptycho_permutation(cp.seed, 1, n_pos)
+    model = pass_model(n, k, False, s["positions"], order, batch)
+    model["flop"] += float(n_pos * (16 * k + 40) * nn)
+    union_total = (pass_model(n, 0, False, s["positions"], order, batch)["bytes_min"] - 12 * nn * n_pos) // 16
+    extra = n_pos * (8 * k + 16) * nn + 8 * union_total + ((n_pos + batch - 1) // batch) * 16 * k * nn
+    model["bytes_min"] += extra
+    model["bytes_pass"] += extra
+    return {"workload": "pc-LSQML on the far-field 1024^2 / 256^2 / K=4 / 1600-position workload, batch "
+                        f"{batch}, damping {lam}, gammas 0.1, constraint and orthogonalisation every iteration",
+            "iterations": iters, "value": round(n_pos * k * iters / wall, 1), "unit": "mode-pattern updates/s",
+            "ms_per_iteration": round(ms, 3), "graded": graded(model, ms, copy_gbs),
+            "kernel_ms_per_iteration": {nm: round(v, 4) for nm, (v, c) in prof.items() if c},
+            "last_batch_mean_steps": [round(float(x), 4) for x in mean],
+            "final_data_error": float(errs[-1])}
+
+
 def c1_leg(P, torch, iters=50):
     """The 64^2-frame far-field scan (144^2 object, 10 x 10 raster at 8 px, K = 1, 1e5 counts) at
     batch size 1 -- the paper's sequential loop, 100 dependent updates per iteration -- with the
@@ -734,6 +783,8 @@ def main():
     ap.add_argument("--no-dm", action="store_true", help="skip the pc-DM engine leg")
     ap.add_argument("--no-c1", action="store_true", help="skip the 64^2-frame batch-1 leg")
     ap.add_argument("--no-mono", action="store_true", help="skip the CGLS monochromatisation leg")
+    ap.add_argument("--no-lsqml", action="store_true", help="skip the pc-LSQML engine leg")
+    ap.add_argument("--lsqml-iterations", type=int, default=3)
     ap.add_argument("--dm-iterations", type=int, default=3)
     ap.add_argument("--group-iterations", type=int, default=3)
     ap.add_argument("--batched", action="store_true",
@@ -808,6 +859,9 @@ def main():
         if not args.no_dm:
             print("[bench] pc-DM engine on the headline workload", file=sys.stderr, flush=True)
             out["dm"] = dm_leg(P, torch, s, spec, args.dm_iterations, copy_gbs)
+        if not args.no_lsqml:
+            print("[bench] pc-LSQML engine on the headline workload", file=sys.stderr, flush=True)
+            out["lsqml"] = lsqml_leg(P, torch, s, spec, args.lsqml_iterations, copy_gbs)
         if not args.no_mono:
             print("[bench] CGLS monochromatisation of the headline patterns", file=sys.stderr, flush=True)
             out["monochromatisation"] = mono_leg(P, torch, s, spec, copy_gbs)

@@ -52,8 +52,13 @@ typedef enum {
 enum { PTYCHO_FAR_FIELD = 0, PTYCHO_NEAR_FIELD = 1 };
 enum { PTYCHO_BLUR_AMPLITUDE = 0 /* Eq. (6) */, PTYCHO_BLUR_INTENSITY = 1 /* Eq. (2) */ };
 enum { PTYCHO_MEM_HOST = 0, PTYCHO_MEM_DEVICE = 1 };
-/* Reconstruction engine (Sec. 4.5: the method plugs into ePIE, rPIE and DM). */
-enum { PTYCHO_ENGINE_EPIE = 0 /* pc-ePIE; pc-rPIE through gamma < 1 */, PTYCHO_ENGINE_DM = 1 /* pc-DM */ };
+/* Reconstruction engine (Sec. 3.2, 4.1 and 4.5: the method plugs into ePIE, rPIE,
+ * DM and LSQML). */
+enum {
+  PTYCHO_ENGINE_EPIE = 0 /* pc-ePIE; pc-rPIE through gamma < 1 */,
+  PTYCHO_ENGINE_DM = 1 /* pc-DM */,
+  PTYCHO_ENGINE_LSQML = 2 /* pc-LSQML (mixed-state with K > 1) */
+};
 
 typedef struct ptycho_params {
   /* Frame side n (probe, box and pattern, Fig. 1): 8, 16, 24, 32, 48, 64, 96,
@@ -104,12 +109,26 @@ typedef struct ptycho_params {
    * gamma_probe, obj_step, probe_step and dft_bf16 do not apply (dft_bf16 must be 0). */
   int32_t engine;
   float dm_reg; /* pc-DM Tikhonov weight of the overlap projection, > 0 (default 1e-3) */
+  /* PTYCHO_ENGINE_LSQML: the least-squares engine of the paper's ref. [27] with
+   * boxes 1 and 2 (pc-LSQML, Sec. 3.2 and 4.1), batch by batch over the same
+   * batches as pc-ePIE.  Per batch, from the same (O, P): the exit-wave updates
+   * chi = psi' - psi of box 1; the directions
+   * dO = N_O / ((1 - gamma_obj) W + gamma_obj max W) on the union of the boxes and
+   * dP_k = N_P,k / ((1 - gamma_probe) V + gamma_probe max V) (sums as for pc-ePIE,
+   * with chi for dpsi); per position j the real steps (a_j, b_j) minimising
+   * sum_k ||chi_jk - a dO_j P_k - b o_j dP_k||^2 with the diagonal of the 2x2
+   * normal equations scaled by (1 + lsq_damping) (b = 0 before
+   * probe_update_start); then O += obj_step mean(a) dO, P_k += probe_step
+   * mean(b) dP_k, and the complex constraint inside its windows.  Modes are
+   * orthogonalised and E_t recorded as for pc-ePIE.  Either propagation path. */
+  float lsq_damping; /* pc-LSQML diagonal damping lambda of the step solve, >= 0 (default 0.1) */
 } ptycho_params;
 
 /* Fill *p with defaults: n = 64, K = 1, far field, sigma 1, kernel 11, amplitude
  * blur, eps 1e-6, alpha1 = 1, alpha2 = 0 (phase object, Sec. 3.1), C-bar in
  * [0.01, 10], constraint off, steps 1, gammas 1, probe update from iteration 1,
- * batch 1, orthogonalisation on, seed 0, the ePIE engine, dm_reg 1e-3.
+ * batch 1, orthogonalisation on, seed 0, the ePIE engine, dm_reg 1e-3,
+ * lsq_damping 0.1.
  * n_pos/obj_h/obj_w are set to 0. */
 void ptycho_default_params(ptycho_params* p);
 
@@ -171,6 +190,13 @@ ptycho_status ptycho_set_state(ptycho_ctx* ctx, const float* object, const float
  * the exit waves to P_k o_n of the new object and probe.)  Synchronise the stream. */
 ptycho_status ptycho_get_exit_waves(ptycho_ctx* ctx, float* out, int32_t mem_kind);
 ptycho_status ptycho_set_exit_waves(ptycho_ctx* ctx, const float* in, int32_t mem_kind);
+
+/* pc-LSQML engine: the step lengths of the last batch run (Sec. 3.2; the steps of
+ * the paper's ref. [27]): steps (host, may be NULL) [batch][2] gets (a_j, b_j) of
+ * its positions in visiting order (rows past that batch's size keep older values),
+ * mean (host, may be NULL) [2] the means (a_bar, b_bar) the batch moved by.
+ * PTYCHO_E_STATE for other engines.  Synchronises the stream. */
+ptycho_status ptycho_get_lsq_steps(ptycho_ctx* ctx, float* steps, float* mean);
 
 /* Completed-iteration counter of the context (-1 for NULL). */
 int32_t ptycho_iteration(const ptycho_ctx* ctx);

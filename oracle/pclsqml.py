@@ -28,7 +28,8 @@ its Gaussian-noise form; each step is one of ref. [27]'s):
      M11 <- (1 + lam) M11 and M22 <- (1 + lam) M22 (lam = lsq_damping >= 0;
      with lam > 0 the damped matrix is positive definite whenever both
      diagonals are nonzero, by Cauchy-Schwarz).  A direction with zero norm
-     gets a zero step; without probe update b = 0 and a = r1 / M11.
+     gets a zero step; without probe update, or when the damped matrix is
+     singular (possible only without damping), b = 0 and a = r1 / M11.
   4. The batch moves by the mean steps (a_bar, b_bar) over its positions:
        O <- O + obj_step a_bar dO  on the union;  P_k <- P_k + probe_step b_bar dP_k.
   5. Inside a constraint window the complex constraint (box 2) follows, as in
@@ -74,6 +75,10 @@ def lsq_steps(M, r, lam, probe_on):
         return r[0] / m11, 0.0
     if m11 <= 0.0:
         return 0.0, r[1] / m22
+    if m11 * m22 - M[0, 1] * M[1, 0] <= 0.0:
+        # singular (only without damping, when the two directions change the exit
+        # waves in parallel): the object step alone
+        return r[0] / m11, 0.0
     sol = np.linalg.solve(np.array([[m11, M[0, 1]], [M[1, 0], m22]]), r)
     return float(sol[0]), float(sol[1])
 

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 OBJDIR = os.path.join(LIBDIR, "obj")
 LIB = os.path.join(LIBDIR, "libptycho.so")
-SOURCES = ["kernels.hip", "dm.hip", "seq.hip", "mono.hip", "runtime.cpp", "learned_kernels.hip", "learned.cpp"]
+SOURCES = ["kernels.hip", "dm.hip", "seq.hip", "mono.hip", "lsqml.hip", "runtime.cpp", "learned_kernels.hip", "learned.cpp"]
 ARCH = os.environ.get("PTYCHO_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

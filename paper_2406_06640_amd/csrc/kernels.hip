@@ -36,7 +36,7 @@ namespace pty {
 const char* const kKernelNames[KC_COUNT] = {
     "fwd_rows", "fwd_cols", "inv_cols", "inv_rows_update", "obj_probe_update", "complex_constraint",
     "gram", "eig", "mode_remix", "err_reduce", "dft_bf16_gemm", "dft_pointwise", "modulus_factor", "cols_fused",
-    "dm_rows", "dm_overlap", "seq_iteration"};
+    "dm_rows", "dm_overlap", "seq_iteration", "lsq_direction", "lsq_step", "lsq_apply"};
 
 LaunchEvents& launch_events() {
   thread_local LaunchEvents ev;
@@ -695,10 +695,19 @@ __host__ __device__ __forceinline__ int post_probe_blocks(int n, int k) {
   return (groups + px_per - 1) / px_per;
 }
 
-// Probe update of one block of probe pixels: numerator N_P,k = sum_b X[b][k]
-// (a fixed order: four interleaved partial sums over the slots, combined
-// pairwise), P_k += beta N_P,k / ((1-g) V + g max V), and sum_k |P_k|^2 into the
-// probe-power copy that the next batch reads.
+// What k_obj_update does with the batch's sums: the pc-ePIE / pc-rPIE update, or
+// for pc-LSQML the directions dO, dP_k (no state change) and, once the steps are
+// known, the update along them.
+constexpr int kObjEpie = 0, kObjLsqDir = 1, kObjLsqApply = 2;
+
+// Probe side of one block of probe pixels.  kObjEpie and kObjLsqDir: numerator
+// N_P,k = sum_b X[b][k] (a fixed order: four interleaved partial sums over the
+// slots, combined pairwise) over the denominator (1-g) V + g max V; kObjEpie adds
+// probe_step times it to P_k, kObjLsqDir stores it as dP_k with sum_k conj(P_k) dP_k
+// and sum_k |dP_k|^2 per pixel.  kObjLsqApply: P_k += probe_step b dP_k.  The
+// updating modes write sum_k |P_k|^2 into the probe-power copy that the next batch
+// reads.
+template <int MODE>
 __device__ __forceinline__ void probe_update_block(const DevParams& p, const DevBufsG& d, const Batch& bt, int beta,
                                                    float* pk2, float* red) {
   const int n = p.n, K = p.k, ns = bt.ns;
@@ -711,17 +720,18 @@ __device__ __forceinline__ void probe_update_block(const DevParams& p, const Dev
   // every load is issued before the first wait: the V-maximum partials, V and
   // P_k at the thread's pixels, then the slots of the numerator sum
   float mv = 0.f;
-  for (int i = threadIdx.x; i < n_probe_blocks_dev(n); i += kThreads) mv = fmaxf(mv, d.maxv_part[i]);
+  if (MODE != kObjLsqApply)
+    for (int i = threadIdx.x; i < n_probe_blocks_dev(n); i += kThreads) mv = fmaxf(mv, d.maxv_part[i]);
   float2 s[kPostUnroll][kPostPx], pv[kPostPx];
   float vv[kPostPx];
 #pragma unroll
   for (int j = 0; j < kPostPx; ++j) {
-    vv[j] = act ? d.V[pix + j] : 0.f;
+    vv[j] = (act && MODE != kObjLsqApply) ? d.V[pix + j] : 0.f;
     pv[j] = act ? d.probe[(size_t)k * nn + pix + j] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int u = 0; u < kPostUnroll; ++u) s[u][j] = make_float2(0.f, 0.f);
   }
-  if (act) {
+  if (act && MODE != kObjLsqApply) {
     // n is even, so a pixel pair never straddles the frame end and is 16-byte aligned
     const float4* x = reinterpret_cast<const float4*>(d.X + (size_t)k * nn + pix);
     const size_t st = (size_t)K * nn / kPostPx;
@@ -739,18 +749,36 @@ __device__ __forceinline__ void probe_update_block(const DevParams& p, const Dev
     }
     for (; b < ns; ++b) add(s[0], x[(size_t)b * st]);
   }
-  const float maxv = block_max_f(mv, red);
-  float mag2[kPostPx];
+  const float maxv = (MODE != kObjLsqApply) ? block_max_f(mv, red) : 0.f;
+  const float bstep = (MODE == kObjLsqApply) ? p.probe_step * d.lsq_ab[1] : 0.f;
+  float mag2[kPostPx], cr[kPostPx], ci[kPostPx];
 #pragma unroll
   for (int j = 0; j < kPostPx; ++j) {
-    mag2[j] = 0.f;
+    mag2[j] = cr[j] = ci[j] = 0.f;
     if (!act) continue;
-    // partial sums combined pairwise: (s0 + s2) + (s1 + s3)
-    const float2 np = cadd(cadd(s[0][j], s[2][j]), cadd(s[1][j], s[3][j]));
     const size_t q = (size_t)k * nn + pix + j;
     float2 v = pv[j];
+    if (MODE == kObjLsqApply) {
+      const float2 dp = d.lsq_dp[q];
+      v.x += bstep * dp.x;
+      v.y += bstep * dp.y;
+      d.probe[q] = v;
+      mag2[j] = v.x * v.x + v.y * v.y;
+      continue;
+    }
+    // partial sums combined pairwise: (s0 + s2) + (s1 + s3)
+    const float2 np = cadd(cadd(s[0][j], s[2][j]), cadd(s[1][j], s[3][j]));
     d.nP[q] = np;
     const float den = (1.0f - p.gamma_probe) * vv[j] + p.gamma_probe * maxv;
+    if (MODE == kObjLsqDir) {
+      const float2 dp = den > 0.f ? cscale(np, 1.0f / den) : make_float2(0.f, 0.f);
+      d.lsq_dp[q] = dp;
+      const float2 c = cmulc(dp, v);  // conj(P_k) dP_k
+      cr[j] = c.x;
+      ci[j] = c.y;
+      mag2[j] = dp.x * dp.x + dp.y * dp.y;
+      continue;
+    }
     if (den > 0.f) {
       const float sc = p.probe_step / den;
       v.x += sc * np.x;
@@ -759,30 +787,52 @@ __device__ __forceinline__ void probe_update_block(const DevParams& p, const Dev
     }
     mag2[j] = v.x * v.x + v.y * v.y;
   }
+  constexpr int kPlanes = MODE == kObjLsqDir ? 3 : 1;
 #pragma unroll
-  for (int j = 0; j < kPostPx; ++j) pk2[j * kThreads + threadIdx.x] = mag2[j];
+  for (int j = 0; j < kPostPx; ++j) {
+    pk2[j * kThreads + threadIdx.x] = mag2[j];
+    if (kPlanes == 3) {
+      pk2[(kPostPx + j) * kThreads + threadIdx.x] = cr[j];
+      pk2[(2 * kPostPx + j) * kThreads + threadIdx.x] = ci[j];
+    }
+  }
   __syncthreads();
   if (k == 0 && pix < n * n) {
 #pragma unroll
     for (int j = 0; j < kPostPx; ++j) {
-      float pw = 0.f;
-      for (int kk = 0; kk < K; ++kk) pw += pk2[j * kThreads + kk * px_per + px];
-      pw_next[pix + j] = pw;
+      float pw = 0.f, sr = 0.f, si = 0.f;
+      for (int kk = 0; kk < K; ++kk) {
+        pw += pk2[j * kThreads + kk * px_per + px];
+        if (kPlanes == 3) {
+          sr += pk2[(kPostPx + j) * kThreads + kk * px_per + px];
+          si += pk2[(2 * kPostPx + j) * kThreads + kk * px_per + px];
+        }
+      }
+      if (MODE == kObjLsqDir) {
+        d.lsq_dp2[pix + j] = pw;
+        d.lsq_pdp[pix + j] = make_float2(sr, si);
+      } else {
+        pw_next[pix + j] = pw;
+      }
     }
   }
 }
 
 // Object and probe update of a batch in one launch (both read only the state
-// before the batch): blocks [0, probe blocks) update the probe (probe_update_block,
-// only in iterations with probe update); the next blocks, one per object tile,
-// gather the object update over the covering slots in ascending order.  Inside a
-// constraint window a tile also writes its share of the C-bar sums of Eq. (11):
-// each pixel counted once per box that covers it.
+// before the batch): blocks [0, probe blocks) run probe_update_block (only in
+// iterations with probe update); the next blocks, one per object tile, gather the
+// object numerator and weight over the covering slots in ascending order.
+// kObjEpie: O += obj_step N_O / ((1-g) W + g max W); kObjLsqDir: that quotient
+// without the step is stored as dO and O is left; kObjLsqApply: no gather (each
+// pixel's box count only), O += obj_step a dO.  Inside a constraint window the
+// updating modes also write the tile's share of the C-bar sums of Eq. (11), each
+// pixel counted once per box that covers it, and the tile's coverage bitmasks.
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
   __shared__ TileList tl;
   __shared__ float red[kThreads / 64];
   __shared__ double2 redd[kThreads / 64];
-  __shared__ float pk2[kPostPx * kThreads];
+  __shared__ float pk2[(MODE == kObjLsqDir ? 3 : 1) * kPostPx * kThreads];
   Batch bt;
   if (!open_batch(cases, beta, it, bt)) return;
   const DevParams& p = bt.cs->p;
@@ -790,13 +840,13 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
   const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
   const int pb = (bt.flags & FLAG_PROBE) ? post_probe_blocks(p.n, p.k) : 0;
   if ((int)blockIdx.x < pb) {
-    probe_update_block(p, d, bt, beta, pk2, red);
+    probe_update_block<MODE>(p, d, bt, beta, pk2, red);
     return;
   }
   const int tiles = tiles_of(p), tiles_x = tiles_x_of(p);
   const int tile = blockIdx.x - pb;
   if (tile >= tiles) return;
-  const bool cc_sums = (bt.flags & FLAG_CC) != 0;
+  const bool cc_sums = MODE != kObjLsqDir && (bt.flags & FLAG_CC) != 0;
   const int n = p.n;
   const int r0 = (tile / tiles_x) * kObjTile, c0 = (tile % tiles_x) * kObjTile;
   const int cnt = tile_list(d, bt.slots, bt.ns, n, r0, c0, tl);
@@ -809,14 +859,18 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
   const int ty = threadIdx.x / kObjTile, tx = threadIdx.x % kObjTile;
   const int c = c0 + tx;
   // loads that do not depend on the gathers are issued with them: the W-maximum
-  // partials and the tile's object values
+  // partials and the tile's object values (or directions)
   float mw = 0.f;
-  for (int i = threadIdx.x; i < tiles; i += kThreads) mw = fmaxf(mw, d.maxw_part[i]);
-  float2 ov[kTilePix];
+  if (MODE != kObjLsqApply)
+    for (int i = threadIdx.x; i < tiles; i += kThreads) mw = fmaxf(mw, d.maxw_part[i]);
+  float2 ov[kTilePix], dv[kTilePix];
 #pragma unroll
   for (int q = 0; q < kTilePix; ++q) {
     const int r = r0 + ty + q * kTileRowsPerPass;
-    ov[q] = (r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
+    const bool inside = r < p.h_obj && c < p.w_obj;
+    const size_t oi = (size_t)r * p.w_obj + c;
+    ov[q] = (inside && MODE != kObjLsqDir) ? d.obj[oi] : make_float2(0.f, 0.f);
+    dv[q] = (inside && MODE == kObjLsqApply) ? d.lsq_do[oi] : make_float2(0.f, 0.f);
   }
   float w[kTilePix];
   float2 num[kTilePix];
@@ -827,57 +881,79 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
     num[q] = make_float2(0.f, 0.f);
     mult[q] = 0;
   }
-  // slots are visited in ascending order; the loads of kGather slots are issued
-  // together before their (in-order) accumulation
-  constexpr int kGather = 4;
-  const float* pw = d.pw + (size_t)pw_copy(bt.flags, beta) * nn;
-  for (int i0 = 0; i0 < cnt; i0 += kGather) {
-    float wv[kGather][kTilePix];
-    float2 nv[kGather][kTilePix];
-    bool in[kGather][kTilePix];
-#pragma unroll
-    for (int j = 0; j < kGather; ++j) {
-      const int i = i0 + j;
-      const int2 rc = i < cnt ? tl.pos[i] : make_int2(-(1 << 20), -(1 << 20));
-      const float2* dOb = d.dO + (size_t)(i < cnt ? tl.slot[i] : 0) * nn;
-      const int xx = c0 + tx - rc.y;
-#pragma unroll
-      for (int q = 0; q < kTilePix; ++q) {
-        const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
-        in[j][q] = (unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n;
-        wv[j][q] = in[j][q] ? pw[yy * n + xx] : 0.f;
-        nv[j][q] = in[j][q] ? dOb[yy * n + xx] : make_float2(0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kGather; ++j)
+  if (MODE == kObjLsqApply) {
+    const int xx0 = c0 + tx;
+    for (int i = 0; i < cnt; ++i) {
+      const int2 rc = tl.pos[i];
+      const bool col_in = (unsigned)(xx0 - rc.y) < (unsigned)n;
 #pragma unroll
       for (int q = 0; q < kTilePix; ++q)
-        if (in[j][q]) {
-          w[q] += wv[j][q];
-          num[q] = cadd(num[q], nv[j][q]);
-          ++mult[q];
+        mult[q] += (col_in && (unsigned)(r0 + ty + q * kTileRowsPerPass - rc.x) < (unsigned)n) ? 1 : 0;
+    }
+  } else {
+    // slots are visited in ascending order; the loads of kGather slots are issued
+    // together before their (in-order) accumulation
+    constexpr int kGather = 4;
+    const float* pw = d.pw + (size_t)pw_copy(bt.flags, beta) * nn;
+    for (int i0 = 0; i0 < cnt; i0 += kGather) {
+      float wv[kGather][kTilePix];
+      float2 nv[kGather][kTilePix];
+      bool in[kGather][kTilePix];
+#pragma unroll
+      for (int j = 0; j < kGather; ++j) {
+        const int i = i0 + j;
+        const int2 rc = i < cnt ? tl.pos[i] : make_int2(-(1 << 20), -(1 << 20));
+        const float2* dOb = d.dO + (size_t)(i < cnt ? tl.slot[i] : 0) * nn;
+        const int xx = c0 + tx - rc.y;
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q) {
+          const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
+          in[j][q] = (unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n;
+          wv[j][q] = in[j][q] ? pw[yy * n + xx] : 0.f;
+          nv[j][q] = in[j][q] ? dOb[yy * n + xx] : make_float2(0.f, 0.f);
         }
+      }
+#pragma unroll
+      for (int j = 0; j < kGather; ++j)
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q)
+          if (in[j][q]) {
+            w[q] += wv[j][q];
+            num[q] = cadd(num[q], nv[j][q]);
+            ++mult[q];
+          }
+    }
   }
-  const float maxw = block_max_f(mw, red);
+  const float maxw = (MODE != kObjLsqApply) ? block_max_f(mw, red) : 0.f;
   const float gam = p.gamma_obj, step = p.obj_step;
+  const float astep = (MODE == kObjLsqApply) ? p.obj_step * d.lsq_ab[0] : 0.f;
   float sa = 0.f, sp = 0.f;
 #pragma unroll
   for (int q = 0; q < kTilePix; ++q) {
     const int r = r0 + ty + q * kTileRowsPerPass;
     if (!mult[q] || r >= p.h_obj || c >= p.w_obj) continue;
     const size_t oi = (size_t)r * p.w_obj + c;
-    if (dbg.n_obj) {
+    if (MODE != kObjLsqApply && dbg.n_obj) {
       dbg.n_obj[oi] = num[q];
       dbg.w_obj[oi] = w[q];
     }
     float2 o = ov[q];
-    const float den = (1.0f - gam) * w[q] + gam * maxw;
-    if (den > 0.f) {
-      const float s = step / den;
-      o.x += s * num[q].x;
-      o.y += s * num[q].y;
+    if (MODE == kObjLsqApply) {
+      o.x += astep * dv[q].x;
+      o.y += astep * dv[q].y;
       d.obj[oi] = o;
+    } else {
+      const float den = (1.0f - gam) * w[q] + gam * maxw;
+      if (MODE == kObjLsqDir) {
+        d.lsq_do[oi] = den > 0.f ? cscale(num[q], 1.0f / den) : make_float2(0.f, 0.f);
+        continue;
+      }
+      if (den > 0.f) {
+        const float s = step / den;
+        o.x += s * num[q].x;
+        o.y += s * num[q].y;
+        d.obj[oi] = o;
+      }
     }
     if (cc_sums) {
       const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
@@ -1472,10 +1548,20 @@ PTY_DEFINE_LAUNCH(inv_rows)
 PTY_DEFINE_LAUNCH(fwd_cols)
 PTY_DEFINE_LAUNCH(inv_cols)
 
-hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+template <int MODE>
+static hipError_t obj_update_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   const int pb = post_probe_blocks(t.n, t.max_k);
-  pty_launch(k_obj_update, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  pty_launch(k_obj_update<MODE>, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
   return hipGetLastError();
+}
+hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  return obj_update_t<kObjEpie>(cases, t, beta, it, s);
+}
+hipError_t launch_lsq_dir(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  return obj_update_t<kObjLsqDir>(cases, t, beta, it, s);
+}
+hipError_t launch_lsq_apply(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
+  return obj_update_t<kObjLsqApply>(cases, t, beta, it, s);
 }
 hipError_t launch_constraint(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   pty_launch(k_constraint, dim3((t.max_tiles + kCcTiles - 1) / kCcTiles, t.n_cases), dim3(kThreads), 0, s, cases,

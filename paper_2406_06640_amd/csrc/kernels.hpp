@@ -41,6 +41,7 @@ struct DevParams {
   float obj_step, probe_step, gamma_obj, gamma_probe;
   float dm_reg;            // pc-DM: Tikhonov weight delta of the overlap projection (relative to max W, max V)
   int dm_seg_len;          // pc-DM: scan positions per segment of the probe-numerator partial sums
+  float lsq_damping;       // pc-LSQML: diagonal damping of the per-position 2x2 step solve
   float gx[kMaxHalf + 1];  // normalised taps for |dx| = 0..ks_half (x = columns, sigma1)
   float gy[kMaxHalf + 1];  // normalised taps for |dy| = 0..ks_half (y = rows, sigma2)
 };
@@ -73,6 +74,14 @@ struct DevBufs {
   double2* gram_part;  // [pairs][kGramBlocks]
   float2* vmix;        // [K][K] eigenvectors (column j = mode j), float
   double* eig;         // [K] eigenvalues
+  // pc-LSQML engine only (null otherwise)
+  float2* lsq_do;      // [H][W] object direction dO (valid on the batch's union)
+  float2* lsq_dp;      // [K][N][N] probe direction dP_k
+  float2* lsq_pdp;     // [N][N] sum_k conj(P_k) dP_k
+  float* lsq_dp2;      // [N][N] sum_k |dP_k|^2
+  double* lsq_part;    // [B][lsq chunks][5] per-slot partial sums of the step normal equations
+  float* lsq_ab;       // [2] the batch's mean steps (a, b)
+  float* lsq_steps;    // [B][2] the last batch's per-position steps (a_j, b_j)
 };
 
 struct DebugPtrs {
@@ -110,7 +119,8 @@ struct TableShape {
 // Kernel classes (for timing).
 enum KernelClass {
   KC_FWD_ROWS = 0, KC_FWD_COLS, KC_INV_COLS, KC_INV_ROWS, KC_OBJ_UPDATE, KC_CONSTRAINT, KC_GRAM, KC_EIG, KC_REMIX,
-  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_DM_ROWS, KC_DM_OVERLAP, KC_SEQ, KC_COUNT
+  KC_ERR, KC_DFT_GEMM, KC_DFT_OTHER, KC_FACTOR, KC_COLS_FUSED, KC_DM_ROWS, KC_DM_OVERLAP, KC_SEQ, KC_LSQ_DIR,
+  KC_LSQ_STEP, KC_LSQ_APPLY, KC_COUNT
 };
 extern const char* const kKernelNames[KC_COUNT];
 
@@ -159,6 +169,19 @@ hipError_t launch_dm_rows_fwd(const CaseDesc* cases, const TableShape& t, int be
 hipError_t launch_dm_rows_inv(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_dm_init_psi(const DevParams& p, const DevBufs& d, hipStream_t s);
 int dm_segments(int n_pos, int seg_len);
+
+// pc-LSQML engine, batch `beta` after the inverse row pass (or the DFT path's delta
+// pass) has left the per-slot numerators: the directions dO, dP_k (k_obj_update in
+// direction mode), the per-slot partial sums of the step normal equations, the
+// per-slot solves and their mean, and the update along the directions (k_obj_update
+// in apply mode, which also writes the complex constraint's sums).
+constexpr int kLsqChunk = 4096;  // frame pixels per block of the partial sums
+constexpr int kLsqTerms = 5;     // M11, M12, M22, r1, r2
+__host__ __device__ inline int lsq_chunks(int n) { return (n * n + kLsqChunk - 1) / kLsqChunk; }
+hipError_t launch_lsq_dir(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_lsq_sums(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_lsq_solve(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+hipError_t launch_lsq_apply(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 
 // Sequential pc-ePIE for batch size 1 and small far-field frames: one
 // workgroup per case runs a whole iteration (every position in order).

@@ -124,6 +124,10 @@ struct DevBufsG {
   GPtr<float> v_part;
   GPtr<float2> vmix;
   GPtr<double> eig;
+  GPtr<float2> lsq_do, lsq_dp, lsq_pdp;
+  GPtr<float> lsq_dp2;
+  GPtr<double> lsq_part;
+  GPtr<float> lsq_ab, lsq_steps;
 };
 __device__ __forceinline__ DevBufsG global_bufs(const DevBufs& in) {
   DevBufsG d;
@@ -152,6 +156,13 @@ __device__ __forceinline__ DevBufsG global_bufs(const DevBufs& in) {
   d.gram_part = as_global(in.gram_part);
   d.vmix = as_global(in.vmix);
   d.eig = as_global(in.eig);
+  d.lsq_do = as_global(in.lsq_do);
+  d.lsq_dp = as_global(in.lsq_dp);
+  d.lsq_pdp = as_global(in.lsq_pdp);
+  d.lsq_dp2 = as_global(in.lsq_dp2);
+  d.lsq_part = as_global(in.lsq_part);
+  d.lsq_ab = as_global(in.lsq_ab);
+  d.lsq_steps = as_global(in.lsq_steps);
   return d;
 }
 struct DebugPtrsG {

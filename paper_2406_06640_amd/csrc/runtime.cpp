@@ -171,7 +171,10 @@ std::string validate(const ptycho_params* p) {
   if (p->dft_bf16 != 0 && p->dft_bf16 != 1) return "dft_bf16 must be 0 or 1";
   if (p->dft_bf16 && (p->geometry != PTYCHO_FAR_FIELD || !dft_supported(p->n)))
     return "dft_bf16 needs the far field and n in {64, 128, 192, 256}";
-  if (p->engine != PTYCHO_ENGINE_EPIE && p->engine != PTYCHO_ENGINE_DM) return "bad engine";
+  if (p->engine != PTYCHO_ENGINE_EPIE && p->engine != PTYCHO_ENGINE_DM && p->engine != PTYCHO_ENGINE_LSQML)
+    return "bad engine";
+  if (p->engine == PTYCHO_ENGINE_LSQML && !(finite_f(p->lsq_damping) && p->lsq_damping >= 0))
+    return "lsq_damping must be finite and >= 0";
   if (p->engine == PTYCHO_ENGINE_DM) {
     if (!(finite_f(p->dm_reg) && p->dm_reg > 0)) return "dm_reg must be finite and > 0";
     if (p->dft_bf16) return "the pc-DM engine runs the FP32 transforms (dft_bf16 must be 0)";
@@ -340,15 +343,30 @@ std::string launch_middle(ptycho_ctx* tc, const CaseDesc* cases, const TableShap
   return "";
 }
 
+// The updates of batch `beta` once the per-slot numerators are in place: the
+// pc-ePIE / pc-rPIE update, or pc-LSQML's directions, step sums, step solve and
+// update along the directions; then the complex constraint.
+std::string launch_updates(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
+                           hipStream_t s, bool lsq) {
+  if (lsq) {
+    LAUNCH(tc, KC_LSQ_DIR, s, launch_lsq_dir(cases, sh, beta, it, s));
+    LAUNCH(tc, KC_LSQ_STEP, s, launch_lsq_sums(cases, sh, beta, it, s));
+    LAUNCH(tc, KC_LSQ_STEP, s, launch_lsq_solve(cases, sh, beta, it, s));
+    LAUNCH(tc, KC_LSQ_APPLY, s, launch_lsq_apply(cases, sh, beta, it, s));
+  } else {
+    LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
+  }
+  LAUNCH(tc, KC_CONSTRAINT, s, launch_constraint(cases, sh, beta, it, s));
+  return "";
+}
+
 std::string launch_batch(ptycho_ctx* tc, const CaseDesc* cases, const TableShape& sh, int beta, const int* it,
-                         hipStream_t s) {
+                         hipStream_t s, bool lsq = false) {
   LAUNCH(tc, KC_FWD_ROWS, s, launch_fwd_rows(cases, sh, beta, it, s));
   std::string e = launch_middle(tc, cases, sh, beta, it, s);
   if (!e.empty()) return e;
   LAUNCH(tc, KC_INV_ROWS, s, launch_inv_rows(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_CONSTRAINT, s, launch_constraint(cases, sh, beta, it, s));
-  return "";
+  return launch_updates(tc, cases, sh, beta, it, s, lsq);
 }
 
 // Mode orthogonalisation (cases flagged) and the data error of every case.
@@ -476,9 +494,7 @@ std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_blur_apply(cases, sh, beta, it, s));
   LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, true, s));
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_delta(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_OBJ_UPDATE, s, launch_obj_update(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_CONSTRAINT, s, launch_constraint(cases, sh, beta, it, s));
-  return "";
+  return launch_updates(tc, cases, sh, beta, it, s, c->prm.engine == PTYCHO_ENGINE_LSQML);
 }
 
 // One batch of a single context (either propagation path); X is the work-frame
@@ -486,7 +502,7 @@ std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc
 std::string launch_one(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc* cases, float2* X, const TableShape& sh,
                        int beta, int ns, const int* it, hipStream_t s) {
   if (c->prm.dft_bf16) return launch_batch_dft(tc, c, cases, X, sh, beta, ns, it, s);
-  return launch_batch(tc, cases, sh, beta, it, s);
+  return launch_batch(tc, cases, sh, beta, it, s, c->prm.engine == PTYCHO_ENGINE_LSQML);
 }
 
 // One iteration of a single context on stream s from the case table `cases`
@@ -716,6 +732,7 @@ void ptycho_default_params(ptycho_params* p) {
   p->geometry = PTYCHO_FAR_FIELD;
   p->engine = PTYCHO_ENGINE_EPIE;
   p->dm_reg = 1e-3f;
+  p->lsq_damping = 0.1f;
   p->fresnel_px = 0.0;
   p->sigma1 = p->sigma2 = 1.0f;
   p->kernel_size = 11;
@@ -831,6 +848,7 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   dp.probe_step = p.probe_step;
   dp.gamma_obj = p.gamma_obj;
   dp.gamma_probe = p.gamma_probe;
+  dp.lsq_damping = p.lsq_damping;
   gaussian_taps(p.sigma1, dp.ks_half, dp.gx);
   gaussian_taps(p.sigma2, dp.ks_half, dp.gy);
 
@@ -970,6 +988,27 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
     d.np_part = npp;
     d.v_part = vpp;
     INIT_TRY(launch_dm_init_psi(dp, d, s));
+  }
+  if (p.engine == PTYCHO_ENGINE_LSQML) {
+    // pc-LSQML: directions, step partial sums and the steps
+    float2 *ldo = nullptr, *ldp = nullptr, *lpdp = nullptr;
+    float *ldp2 = nullptr, *lab = nullptr, *lst = nullptr;
+    double* lpart = nullptr;
+    if ((st = dev_alloc(c, &ldo, (size_t)p.obj_h * p.obj_w)) || (st = dev_alloc(c, &ldp, K * nn)) ||
+        (st = dev_alloc(c, &lpdp, nn)) || (st = dev_alloc(c, &ldp2, nn)) ||
+        (st = dev_alloc(c, &lpart, (size_t)B * lsq_chunks(n) * kLsqTerms)) || (st = dev_alloc(c, &lab, 2)) ||
+        (st = dev_alloc(c, &lst, (size_t)2 * B)))
+      return bail(st);
+    INIT_TRY(hipMemsetAsync(ldo, 0, (size_t)p.obj_h * p.obj_w * sizeof(float2), s));
+    INIT_TRY(hipMemsetAsync(lab, 0, 2 * sizeof(float), s));
+    INIT_TRY(hipMemsetAsync(lst, 0, (size_t)2 * B * sizeof(float), s));
+    d.lsq_do = ldo;
+    d.lsq_dp = ldp;
+    d.lsq_pdp = lpdp;
+    d.lsq_dp2 = ldp2;
+    d.lsq_part = lpart;
+    d.lsq_ab = lab;
+    d.lsq_steps = lst;
   }
   std::vector<int> hb((size_t)p.n_pos * gx);
   std::vector<double> hs((size_t)p.n_pos * gx);
@@ -1265,6 +1304,18 @@ ptycho_status ptycho_get_exit_waves(ptycho_ctx* c, float* out, int32_t mem_kind)
   if (!out) return fail(c, PTYCHO_E_INVALID, "out is NULL");
   const size_t count = (size_t)c->prm.n_pos * c->prm.n_modes * c->prm.n * c->prm.n;
   HIP_TRY(c, hipMemcpyAsync(out, c->db.psi, count * sizeof(float2), kind_out(mem_kind), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PTYCHO_OK;
+}
+
+ptycho_status ptycho_get_lsq_steps(ptycho_ctx* c, float* steps, float* mean) {
+  if (!c) return fail(nullptr, PTYCHO_E_INVALID, "ctx is NULL");
+  if (c->prm.engine != PTYCHO_ENGINE_LSQML)
+    return fail(c, PTYCHO_E_STATE, "step lengths are state of the pc-LSQML engine only");
+  if (steps)
+    HIP_TRY(c, hipMemcpyAsync(steps, c->db.lsq_steps, (size_t)2 * c->prm.batch * sizeof(float),
+                              hipMemcpyDeviceToHost, c->stream));
+  if (mean) HIP_TRY(c, hipMemcpyAsync(mean, c->db.lsq_ab, 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PTYCHO_OK;
 }

@@ -21,7 +21,8 @@ __all__ = [
     "PTYCHO_OK", "PTYCHO_E_INVALID", "PTYCHO_E_SHAPE", "PTYCHO_E_OOM", "PTYCHO_E_HIP",
     "PTYCHO_E_NUMERIC", "PTYCHO_E_STATE", "PTYCHO_FAR_FIELD", "PTYCHO_NEAR_FIELD",
     "PTYCHO_BLUR_AMPLITUDE", "PTYCHO_BLUR_INTENSITY", "PTYCHO_MEM_HOST", "PTYCHO_MEM_DEVICE",
-    "PTYCHO_ENGINE_EPIE", "PTYCHO_ENGINE_DM", "ptycho_get_exit_waves", "ptycho_set_exit_waves",
+    "PTYCHO_ENGINE_EPIE", "PTYCHO_ENGINE_DM", "PTYCHO_ENGINE_LSQML", "ptycho_get_exit_waves", "ptycho_set_exit_waves",
+    "ptycho_get_lsq_steps",
     "ptycho_mono_create", "ptycho_mono_run", "ptycho_mono_destroy", "Monochromatiser",
     "PtychoParams", "PtychoError", "lib", "library_path", "load_library", "default_params",
     "ptycho_init", "ptycho_iterate", "ptycho_iterate_static", "ptycho_get_object", "ptycho_get_probe", "ptycho_set_state",
@@ -35,7 +36,7 @@ PTYCHO_OK, PTYCHO_E_INVALID, PTYCHO_E_SHAPE, PTYCHO_E_OOM = 0, -1, -2, -3
 PTYCHO_E_HIP, PTYCHO_E_NUMERIC, PTYCHO_E_STATE = -4, -5, -6
 PTYCHO_FAR_FIELD, PTYCHO_NEAR_FIELD = 0, 1
 PTYCHO_BLUR_AMPLITUDE, PTYCHO_BLUR_INTENSITY = 0, 1
-PTYCHO_ENGINE_EPIE, PTYCHO_ENGINE_DM = 0, 1
+PTYCHO_ENGINE_EPIE, PTYCHO_ENGINE_DM, PTYCHO_ENGINE_LSQML = 0, 1, 2
 PTYCHO_MEM_HOST, PTYCHO_MEM_DEVICE = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,7 +61,7 @@ class PtychoParams(ctypes.Structure):
         ("probe_update_start", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("orthogonalize", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("dft_bf16", ctypes.c_int32),
-        ("engine", ctypes.c_int32), ("dm_reg", ctypes.c_float),
+        ("engine", ctypes.c_int32), ("dm_reg", ctypes.c_float), ("lsq_damping", ctypes.c_float),
     ]
 
 
@@ -91,6 +92,7 @@ def load_library():
         "ptycho_iterate": (i32, [vp, i32, fp, fp]),
         "ptycho_iterate_static": (i32, [vp, i32, fp, fp]),
         "ptycho_get_exit_waves": (i32, [vp, fp, i32]),
+        "ptycho_get_lsq_steps": (i32, [vp, fp, fp]),
         "ptycho_mono_create": (i32, [i32, i32, fp, fp, i32, vp, P(vp)]),
         "ptycho_mono_run": (i32, [vp, fp, fp, i32, i32, fp, i32]),
         "ptycho_mono_destroy": (None, [vp]),
@@ -237,6 +239,14 @@ def ptycho_get_exit_waves(ctx, out):
     mk = PTYCHO_MEM_DEVICE if _is_torch(out) else PTYCHO_MEM_HOST
     _check(load_library().ptycho_get_exit_waves(ctx, _out_ptr(out, mk), mk), ctx)
     return out
+
+
+def ptycho_get_lsq_steps(ctx, batch):
+    """pc-LSQML step lengths of the last batch run: ([batch][2] (a_j, b_j), [2] means)."""
+    steps = np.zeros((batch, 2), dtype=np.float32)
+    mean = np.zeros(2, dtype=np.float32)
+    _check(load_library().ptycho_get_lsq_steps(ctx, steps.ctypes.data, mean.ctypes.data), ctx)
+    return steps, mean
 
 
 def ptycho_set_exit_waves(ctx, psi, mem_kind=PTYCHO_MEM_HOST):
@@ -439,6 +449,10 @@ class Reconstruction:
 
     def set_exit_waves(self, psi):
         ptycho_set_exit_waves(self.ctx, psi)
+
+    def lsq_steps(self):
+        """pc-LSQML: the last batch's per-position steps [batch][2] and their means [2]."""
+        return ptycho_get_lsq_steps(self.ctx, self.params.batch)
 
     def set_graph(self, enable=True):
         ptycho_set_graph(self.ctx, enable)

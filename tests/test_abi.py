@@ -37,6 +37,7 @@ def test_defaults():
     assert (p.n, p.n_modes, p.kernel_size, p.batch, p.probe_update_start) == (64, 1, 11, 1, 1)
     assert p.sigma1 == 1.0 and p.sigma2 == 1.0 and p.alpha1 == 1.0 and p.alpha2 == 0.0
     assert abs(p.eps - 1e-6) < 1e-12 and p.cc_start == 0 and p.gamma_obj == 1.0
+    assert p.engine == P.PTYCHO_ENGINE_EPIE and abs(p.dm_reg - 1e-3) < 1e-9 and abs(p.lsq_damping - 0.1) < 1e-7
 
 
 def test_permutation_matches_oracle_generator():
@@ -66,6 +67,8 @@ def _arrays(n=16, n_pos=2, obj=32, k=1):
     (dict(kernel_size=33), -1), (dict(alpha1=1.5), -1), (dict(gamma_obj=0.0), -1), (dict(batch=0), -1),
     (dict(batch=257), -1), (dict(cbar_min=0.0), -1), (dict(sigma1=-1.0), -1), (dict(geometry=1), -1),
     (dict(obj_h=8), -1), (dict(sigma2=float("nan")), -1), (dict(orthogonalize=2), -1),
+    (dict(engine=3), -1), (dict(engine=2, lsq_damping=-0.5), -1), (dict(engine=2, lsq_damping=float("inf")), -1),
+    (dict(engine=1, dm_reg=0.0), -1), (dict(engine=1, dft_bf16=1, n=64, obj_h=128, obj_w=128), -1),
 ])
 def test_invalid_parameters_rejected_before_device_work(kw, status):
     import paper_2406_06640_amd as P
@@ -97,6 +100,7 @@ def test_null_context_calls_fail_cleanly():
     import paper_2406_06640_amd as P
     lib = P.load_library()
     assert lib.ptycho_iterate(None, 1, None, None) == P.PTYCHO_E_INVALID
+    assert lib.ptycho_get_lsq_steps(None, None, None) == P.PTYCHO_E_INVALID
     assert lib.ptycho_iteration(None) == -1
     lib.ptycho_destroy(None)
     assert P.ptycho_last_error(None)
