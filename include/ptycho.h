@@ -302,7 +302,7 @@ ptycho_status ptycho_dft2_bf16(float* frames_inout, int32_t n, int32_t frames, i
  * pixel (n/2, n/2) by s_j = lambda_c / lambda_j and weighted by w_j s_j^2
  * (sum w_j = 1, so each wavelength carries its weight's power), sampled
  * bilinearly with zero outside the frame; C^T is its exact adjoint.
- *  create: n even in [2, 4096]; max_patterns >= 1; scales[n_lambda] in [1/16, 16]
+ *  create: n even in [2, 4096]; max_patterns in [1, 65535]; scales[n_lambda] in [1/16, 16]
  *          and weights[n_lambda] >= 0 (normalised here), host arrays, n_lambda in
  *          [1, 16]; hip_stream orders every call (NULL = null stream).  Owns
  *          6 x max_patterns x n^2 floats of device work and staging memory and

@@ -208,8 +208,12 @@ struct MonoTables {
   int* adj_cnt;   // [count][n] run length up to the last nonzero weight
   float* adj_w;   // [count][n][adj_stride]
   int adj_stride; // floor(2 / min scale) + 3
+  int adj_max;    // largest adj_cnt (read back at plan creation)
 };
 int mono_adj_stride(const MonoSpectrum& sp);
+// Partial sums per pattern that the CGLS kernels write (the larger of the operator's
+// tiles and the element-wise kernels' blocks).
+int mono_part_count(int n);
 struct MonoWork {
   MonoSpectrum spec;
   MonoTables tab;

@@ -1833,7 +1833,7 @@ ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* s
   if (out) *out = nullptr;
   if (!out || !scales || !weights) return fail(nullptr, PTYCHO_E_INVALID, "NULL argument");
   if (n < 2 || n > 4096 || (n & 1)) return fail(nullptr, PTYCHO_E_SHAPE, "n must be even and in [2, 4096]");
-  if (max_patterns < 1) return fail(nullptr, PTYCHO_E_SHAPE, "max_patterns must be >= 1");
+  if (max_patterns < 1 || max_patterns > 65535) return fail(nullptr, PTYCHO_E_SHAPE, "max_patterns must be in [1, 65535]");
   if (n_lambda < 1 || n_lambda > kMonoMaxLambda) return fail(nullptr, PTYCHO_E_INVALID, "n_lambda must be in [1, 16]");
   double wsum = 0.0;
   for (int j = 0; j < n_lambda; ++j) {
@@ -1853,7 +1853,7 @@ ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* s
     m->w.spec.coef[j] = (float)(weights[j] / wsum * (double)scales[j] * (double)scales[j]);
   }
   const size_t nn = (size_t)n * n, tot = nn * max_patterns;
-  const size_t blocks = (nn + 255) / 256;
+  const size_t blocks = (size_t)mono_part_count(n);
   auto alloc = [&](void** p, size_t bytes) {
     if (hipMalloc(p, bytes) != hipSuccess) return false;
     m->allocs.push_back(*p);
@@ -1877,7 +1877,11 @@ ptycho_status ptycho_mono_create(int32_t n, int32_t max_patterns, const float* s
     return fail(nullptr, PTYCHO_E_OOM, "device allocation failed");
   }
   hipError_t e = launch_mono_tables(m->w, n, m->stream);
+  std::vector<int> hcnt(tn);
+  if (e == hipSuccess) e = hipMemcpyAsync(hcnt.data(), tb.adj_cnt, tn * sizeof(int), hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  tb.adj_max = 0;
+  for (int c : hcnt) tb.adj_max = std::max(tb.adj_max, c);
   if (e != hipSuccess) {
     ptycho_mono_destroy(m);
     return fail(nullptr, PTYCHO_E_HIP, std::string("monochromatisation tables: ") + hipGetErrorString(e));

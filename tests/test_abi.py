@@ -161,6 +161,7 @@ def test_forward_model_config_validation(field, value, status):
 @pytest.mark.parametrize("n,count,scales,weights,status", [
     (31, 4, [1.0], [1.0], -2),                     # n odd
     (32, 0, [1.0], [1.0], -2),                     # no patterns
+    (32, 70000, [1.0], [1.0], -2),                 # more patterns than one launch's grid rows
     (32, 4, [1.0, 0.05], [1.0, 1.0], -1),          # scale below 1/16
     (32, 4, [20.0], [1.0], -1),                    # scale above 16
     (32, 4, [1.0, 1.1], [0.0, 0.0], -1),           # all weights zero
