@@ -100,14 +100,19 @@ struct ptycho_group {
     bool seq = false;          // members run whole iterations in the sequential kernel
     CaseDesc* d_cases = nullptr;
     CaseDesc* h_cases = nullptr;  // pinned
+    int max_nb = 0;               // batches per iteration of its member with the most
   };
   std::vector<Table> tables;
+  // tables run concurrently, table i on side[i % side.size()], forked from and joined
+  // back into the calling stream each iteration (no side streams for one table)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork = nullptr;
   hipStream_t stream = nullptr;
   CallBufs call;
   int* d_iter = nullptr;
   std::vector<void*> allocs;
   std::string err;
-  int max_nb = 0;  // batches per iteration of the member with the most
   // iteration replay from a captured graph
   bool use_graph = false;
   hipStream_t gstream = nullptr;
@@ -412,6 +417,8 @@ bool seq_eligible(const ptycho_params& p) {
 }
 // Launch variant index of the sequential kernel (after the batch-pass variants).
 constexpr int kSeqVariant = kColVariants;
+// Side streams of a group (one frame-size class each; within the box's hardware queues).
+constexpr size_t kGroupStreams = 4;
 
 // Fill the per-case fields of a table entry for the current call.
 void fill_case(const ptycho_ctx* c, CaseDesc& cd, const int* order, const int* flags, float* err) {
@@ -1606,6 +1613,20 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
     sh.max_k = std::max(sh.max_k, c->prm.n_modes);
     sh.max_side_jobs = std::max(sh.max_side_jobs, n_obj_tiles(c->dp) + n_probe_blocks(c->prm.n));
     sh.max_half = std::max(sh.max_half, c->dp.ks_half);
+    tb.max_nb = std::max(tb.max_nb, n_batches_of(c->prm));
+  }
+  if (g->tables.size() > 1) {
+    const size_t ns = std::min<size_t>(g->tables.size(), kGroupStreams);
+    g->side.assign(ns, nullptr);
+    g->side_done.assign(ns, nullptr);
+    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+    for (size_t i = 0; ok && i < ns; ++i)
+      ok = hipStreamCreateWithFlags(&g->side[i], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&g->side_done[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      ptycho_group_destroy(g);
+      return gfail(nullptr, PTYCHO_E_HIP, "group stream creation failed");
+    }
   }
   for (auto& tb : g->tables) {
     void* p = nullptr;
@@ -1636,23 +1657,43 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
 
 namespace {
 
-// One iteration of every member: batches in lockstep over the tables, then
-// each table's end-of-iteration work, then the iteration counter.
-std::string enqueue_group_iteration(ptycho_group* g, hipStream_t s) {
-  for (auto& tb : g->tables)
-    if (tb.seq) {  // whole iterations of every member, one workgroup per case
-      const hipError_t he = launch_seq_iter(tb.d_cases, tb.shape, g->d_iter, s);
-      if (he != hipSuccess) return std::string("seq_iteration: ") + hipGetErrorString(he);
-    }
-  for (int beta = 0; beta < g->max_nb; ++beta)
-    for (auto& tb : g->tables) {
-      if (tb.seq) continue;
+// One iteration of one table on stream s: the sequential kernel (one workgroup per
+// case) or the batches in order, then the end-of-iteration work.
+std::string enqueue_table_iteration(ptycho_group* g, ptycho_group::Table& tb, hipStream_t s) {
+  if (tb.seq) {
+    const hipError_t he = launch_seq_iter(tb.d_cases, tb.shape, g->d_iter, s);
+    if (he != hipSuccess) return std::string("seq_iteration: ") + hipGetErrorString(he);
+  } else {
+    for (int beta = 0; beta < tb.max_nb; ++beta) {
       std::string e = launch_batch(nullptr, tb.d_cases, tb.shape, beta, g->d_iter, s);
       if (!e.empty()) return e;
     }
-  for (auto& tb : g->tables) {
-    std::string e = launch_end(nullptr, tb.d_cases, tb.shape, g->d_iter, s);
+  }
+  return launch_end(nullptr, tb.d_cases, tb.shape, g->d_iter, s);
+}
+
+// One iteration of every member: the tables (independent cases, each with its own
+// buffers) on their side streams at once, joined before the iteration counter
+// advances.  Each table's kernels run in the same order as alone, so results do not
+// depend on the overlap.
+std::string enqueue_group_iteration(ptycho_group* g, hipStream_t s) {
+  const size_t ns = g->side.size();
+  if (ns == 0) {
+    std::string e = enqueue_table_iteration(g, g->tables[0], s);
     if (!e.empty()) return e;
+  } else {
+    hipError_t he = hipEventRecord(g->fork, s);
+    for (size_t i = 0; he == hipSuccess && i < ns; ++i) he = hipStreamWaitEvent(g->side[i], g->fork, 0);
+    if (he != hipSuccess) return std::string("group fork: ") + hipGetErrorString(he);
+    for (size_t i = 0; i < g->tables.size(); ++i) {
+      std::string e = enqueue_table_iteration(g, g->tables[i], g->side[i % ns]);
+      if (!e.empty()) return e;
+    }
+    for (size_t i = 0; he == hipSuccess && i < ns; ++i) {
+      he = hipEventRecord(g->side_done[i], g->side[i]);
+      if (he == hipSuccess) he = hipStreamWaitEvent(s, g->side_done[i], 0);
+    }
+    if (he != hipSuccess) return std::string("group join: ") + hipGetErrorString(he);
   }
   const hipError_t he = launch_iter_advance(g->d_iter, s);
   return he == hipSuccess ? std::string() : std::string("iteration counter: ") + hipGetErrorString(he);
@@ -1714,7 +1755,6 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
   for (int i = 0; i < nc; ++i) off[i + 1] = off[i] + (size_t)n_iter * g->ctx[i]->prm.n_pos;
   if (!grow_call(g, g->allocs, g->call, off[nc], (size_t)n_iter * nc))
     return gfail(g, PTYCHO_E_OOM, "schedule buffer allocation failed");
-  int max_nb = 0;
   for (int i = 0; i < nc; ++i) {
     ptycho_ctx* c = g->ctx[i];
     const int np = c->prm.n_pos;
@@ -1729,7 +1769,6 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
       f = with_pw_parity(f, par, nb);
     }
     c->pw_par_next = par;
-    if (!c->seq) max_nb = std::max(max_nb, n_batches_of(c->prm));
   }
   for (auto& tb : g->tables)
     for (size_t m = 0; m < tb.members.size(); ++m) {
@@ -1744,7 +1783,6 @@ ptycho_status ptycho_group_iterate(ptycho_group* g, int32_t n_iter, float* err_o
   for (auto& tb : g->tables)
     HIP_GTRY(g, hipMemcpyAsync(tb.d_cases, tb.h_cases, tb.members.size() * sizeof(CaseDesc), hipMemcpyHostToDevice, s));
   HIP_GTRY(g, launch_iter_set(g->d_iter, 0, s));
-  g->max_nb = max_nb;
   if (g->use_graph) {
     ptycho_status gs = build_group_graph(g);
     if (gs != PTYCHO_OK) return gs;
@@ -1781,8 +1819,15 @@ void ptycho_group_destroy(ptycho_group* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
   if (g->gstream) (void)hipStreamSynchronize(g->gstream);
+  for (hipStream_t st : g->side)
+    if (st) (void)hipStreamSynchronize(st);
   drop_group_graph(g);
   if (g->gstream) (void)hipStreamDestroy(g->gstream);
+  for (hipStream_t st : g->side)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : g->side_done)
+    if (ev) (void)hipEventDestroy(ev);
+  if (g->fork) (void)hipEventDestroy(g->fork);
   if (g->ev_in) (void)hipEventDestroy(g->ev_in);
   if (g->ev_out) (void)hipEventDestroy(g->ev_out);
   for (auto& tb : g->tables)
