@@ -245,9 +245,8 @@ __global__ __launch_bounds__(kThreads) void k_dm_obj(const CaseDesc* __restrict_
       d.obj[(size_t)r * p.w_obj + c] = o;
     }
     if (cc_sums) {
-      const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
-      sa += mult[q] * fabsf(logf(a));
-      sp += mult[q] * fabsf(atan2f(o.y, o.x));
+      sa += mult[q] * fabsf(cc_ln_amp(o));
+      sp += mult[q] * fabsf(cc_phase(o));
     }
   }
   if (cc_sums) {

@@ -956,9 +956,8 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
       }
     }
     if (cc_sums) {
-      const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
-      sa += mult[q] * fabsf(logf(a));
-      sp += mult[q] * fabsf(atan2f(o.y, o.x));
+      sa += mult[q] * fabsf(cc_ln_amp(o));
+      sp += mult[q] * fabsf(cc_phase(o));
     }
   }
   if (cc_sums) {
@@ -1037,14 +1036,7 @@ __global__ __launch_bounds__(kThreads) void k_constraint(const CaseDesc* __restr
       const int e = u * kTilePix + q;
       if (!((rowm[e] >> tx) & 1u)) continue;  // outside the union of the boxes (or the object)
       const int r = r0 + ty + q * kTileRowsPerPass;
-      const float2 o = ov[e];
-      const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
-      const float phi = atan2f(o.y, o.x);
-      const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
-      const float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
-      float sn, cs;
-      sincosf(pc, &sn, &cs);
-      d.obj[(size_t)r * p.w_obj + c] = make_float2(ac * cs, ac * sn);
+      d.obj[(size_t)r * p.w_obj + c] = cc_apply(ov[e], cbar, inv_c, a1, a2);
     }
   }
 }

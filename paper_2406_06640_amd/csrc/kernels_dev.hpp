@@ -54,6 +54,27 @@ struct ColW {
   static constexpr int C = VALID ? W0 : Cfg<N>::COLS;
 };
 
+// The complex constraint's per-pixel quantities (Eq. 9-11): the logarithm of the
+// amplitude floored at 1e-20, the principal phase, and Eq. (9)-(10),
+//   A^c = exp[(1 - a1) ln A + a1 C phi],  phi^c = (1 - a2) phi + a2 ln A / C,
+// with the hardware base-2 logarithm, exponential, sine and cosine (v_log_f32,
+// v_exp_f32, v_sin_f32, v_cos_f32: about 1e-6 relative on these arguments; the
+// phase is reduced to [-pi, pi] first, inside the sine's valid range).
+__device__ __forceinline__ float cc_ln_amp(float2 o) {
+  return __logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
+}
+__device__ __forceinline__ float cc_phase(float2 o) { return atan2f(o.y, o.x); }
+__device__ __forceinline__ float2 cc_apply(float2 o, float cbar, float inv_c, float a1, float a2) {
+  const float lna = cc_ln_amp(o);
+  const float phi = cc_phase(o);
+  const float ac = __expf((1.0f - a1) * lna + a1 * cbar * phi);
+  float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
+  if (fabsf(pc) > 3.14159265f) pc -= 6.28318531f * rintf(pc * 0.159154943f);
+  float sn, cs;
+  __sincosf(pc, &sn, &cs);
+  return make_float2(ac * cs, ac * sn);
+}
+
 // Block reductions in a fixed order: butterfly over the 64 lanes of each wave,
 // then the 4 wave results in order.  `sh` holds kThreads / 64 entries.
 __device__ __forceinline__ double block_sum_d(double v, double* sh) {

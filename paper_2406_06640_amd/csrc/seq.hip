@@ -268,9 +268,8 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
       }
       onew[s] = o;
       if (cc) {
-        const float a = fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f);
-        sa += fabsf(logf(a));
-        sp += fabsf(atan2f(o.y, o.x));
+        sa += fabsf(cc_ln_amp(o));
+        sp += fabsf(cc_phase(o));
       }
     });
     if (cc) {
@@ -282,14 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
         const float inv_c = 1.0f / cbar;
         const float a1 = p.alpha1, a2 = p.alpha2;
         for_store_slots<N, N, false>([&](int s, int y, int x) {
-          const float2 o = onew[s];
-          const float lna = logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
-          const float phi = atan2f(o.y, o.x);
-          const float ac = expf((1.0f - a1) * lna + a1 * cbar * phi);
-          const float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
-          float sn, cs2;
-          sincosf(pc, &sn, &cs2);
-          d.obj[(size_t)(rc.x + y) * W + rc.y + x] = make_float2(ac * cs2, ac * sn);
+          d.obj[(size_t)(rc.x + y) * W + rc.y + x] = cc_apply(onew[s], cbar, inv_c, a1, a2);
         });
       }
     }
