@@ -64,15 +64,16 @@ __device__ __forceinline__ float cc_ln_amp(float2 o) {
   return __logf(fmaxf(sqrtf(o.x * o.x + o.y * o.y), 1e-20f));
 }
 __device__ __forceinline__ float cc_phase(float2 o) { return atan2f(o.y, o.x); }
-__device__ __forceinline__ float2 cc_apply(float2 o, float cbar, float inv_c, float a1, float a2) {
-  const float lna = cc_ln_amp(o);
-  const float phi = cc_phase(o);
+__device__ __forceinline__ float2 cc_apply_lp(float lna, float phi, float cbar, float inv_c, float a1, float a2) {
   const float ac = __expf((1.0f - a1) * lna + a1 * cbar * phi);
   float pc = (1.0f - a2) * phi + a2 * inv_c * lna;
   if (fabsf(pc) > 3.14159265f) pc -= 6.28318531f * rintf(pc * 0.159154943f);
   float sn, cs;
   __sincosf(pc, &sn, &cs);
   return make_float2(ac * cs, ac * sn);
+}
+__device__ __forceinline__ float2 cc_apply(float2 o, float cbar, float inv_c, float a1, float a2) {
+  return cc_apply_lp(cc_ln_amp(o), cc_phase(o), cbar, inv_c, a1, a2);
 }
 
 // Block reductions in a fixed order: butterfly over the 64 lanes of each wave,

@@ -29,15 +29,17 @@ bool seq_supported(int n, bool near_field) {
   return !near_field && (n == 16 || n == 32 || n == 48 || n == 64);
 }
 
+constexpr int kSlideHalf = 5;  // blur half-width held in the sliding windows
+
 template <int N>
 struct SeqLds {
   using RowF = Frame<N, N, false>;
   using ColF = Frame<N, N, true>;
   static constexpr int ROW = RowF::ELEMS;  // float2, row-pass layout
   static constexpr int COL = ColF::ELEMS;  // float2, column-pass layout
-  // tw [N] | row buffer | column buffer | box [N^2] float2 | mode-0 frame [N^2] float2 | factor [N^2] float
+  // tw [N] | row buffer | column buffer | box [N^2] float2 | mode-0 frame [N^2] float2 | factor [N][N + 1] float
   static constexpr size_t BYTES =
-      sizeof(float2) * ((size_t)N + ROW + COL + 2 * (size_t)N * N) + sizeof(float) * (size_t)N * N;
+      sizeof(float2) * ((size_t)N + ROW + COL + 2 * (size_t)N * N) + sizeof(float) * (size_t)N * (N + 1);
 };
 
 template <int N>
@@ -48,6 +50,15 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
   constexpr int LR = RegShape<N, N>::LOAD_SLOTS;
   constexpr int NN = N * N;
   constexpr int EP = (NN + kThreads - 1) / kThreads;  // plain elements per thread
+  // Blur by sliding windows when the frame splits into whole line segments: a thread
+  // owns RL consecutive elements of one column (vertical pass) and then of one row
+  // (horizontal pass), loads its window once and applies every tap from registers.
+  // Windows hold kSlideHalf taps each side (the paper's 11 x 11 kernel); wider
+  // kernels take the per-tap path.
+  constexpr bool SLIDE = kThreads % N == 0 && NN % kThreads == 0;
+  constexpr int RL = SLIDE ? NN / kThreads : 1;  // elements per thread along a line
+  constexpr int WL = RL + 2 * kSlideHalf;        // window length
+  constexpr int S1 = N + 1;                      // padded row stride (horizontal pass input, factor)
   extern __shared__ float2 sm[];
   __shared__ double red[kThreads / 64];
   __shared__ double2 redd[kThreads / 64];
@@ -96,7 +107,8 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
         if (NN % kThreads != 0 && e >= NN) continue;
         const int y = e / N, x = e - y * N;
         ob[j] = d.obj[(size_t)(rc.x + y) * W + rc.y + x];
-        av[j] = amp[e];
+        // sliding layout: row threadIdx.x % N, columns (threadIdx.x / N) RL + j
+        av[j] = SLIDE ? amp[(threadIdx.x % N) * N + (threadIdx.x / N) * RL + j] : amp[e];
       }
 #pragma unroll
       for (int j = 0; j < EP; ++j) {
@@ -142,65 +154,115 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
     // box 1: mode sum -> blur (vertical, then horizontal) -> modulus factor; data error
     for_store_slots<N, N, true>([&](int s, int u, int y) { t0[y * N + u] = inten ? acc[s] : sqrtf(acc[s]); });
     __syncthreads();
-    {
-      float gv[EP];
-#pragma unroll
-      for (int j = 0; j < EP; ++j) {
-        const int e = threadIdx.x + j * kThreads;
-        gv[j] = (NN % kThreads != 0 && e >= NN) ? 0.f : sgy[0] * t0[e];
-      }
-      for (int dy = 1; dy <= h; ++dy) {
-        const float gd = sgy[dy];
-#pragma unroll
-        for (int j = 0; j < EP; ++j) {
-          const int e = threadIdx.x + j * kThreads;
-          if (NN % kThreads != 0 && e >= NN) continue;
-          const int y = e / N, x = e - y * N;
-          gv[j] += gd * (t0[wrap(y - dy, N) * N + x] + t0[wrap(y + dy, N) * N + x]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < EP; ++j) {
-        const int e = threadIdx.x + j * kThreads;
-        if (NN % kThreads == 0 || e < NN) t1[e] = gv[j];
-      }
-    }
-    __syncthreads();
     double err = 0.0;
-    {
-      float gv[EP];
-#pragma unroll
-      for (int j = 0; j < EP; ++j) {
-        const int e = threadIdx.x + j * kThreads;
-        gv[j] = (NN % kThreads != 0 && e >= NN) ? 0.f : sgx[0] * t1[e];
+    // modulus factor and data error of element (y, x) from its blurred value g
+    auto factor_at = [&](int y, int x, float g, float a) {
+      float ag, f;
+      if (inten) {
+        ag = sqrtf(g);
+        f = a / sqrtf(g + p.eps * p.eps);
+      } else {
+        ag = g;
+        f = a / (g + p.eps);
       }
-      for (int dx = 1; dx <= h; ++dx) {
-        const float gd = sgx[dx];
+      fbuf[y * S1 + x] = f;
+      const double dd = (double)a - (double)ag;
+      err += dd * dd;
+    };
+    if (SLIDE && h <= kSlideHalf) {
+      float* t1p = t1;  // [N][S1]
+      {
+        const int x = threadIdx.x % N, y0 = (threadIdx.x / N) * RL;
+        float win[WL];
+#pragma unroll
+        for (int i = 0; i < WL; ++i) {
+          const int off = i - kSlideHalf;
+          win[i] = (off >= -h && off < RL + h) ? t0[wrap(y0 + off, N) * N + x] : 0.f;
+        }
+        float gv[RL];
+#pragma unroll
+        for (int i = 0; i < RL; ++i) gv[i] = sgy[0] * win[i + kSlideHalf];
+#pragma unroll
+        for (int dy = 1; dy <= kSlideHalf; ++dy) {
+          if (dy > h) break;
+          const float gd = sgy[dy];
+#pragma unroll
+          for (int i = 0; i < RL; ++i) gv[i] += gd * (win[i + kSlideHalf - dy] + win[i + kSlideHalf + dy]);
+        }
+#pragma unroll
+        for (int i = 0; i < RL; ++i) t1p[(y0 + i) * S1 + x] = gv[i];
+      }
+      __syncthreads();
+      {
+        const int y = threadIdx.x % N, x0 = (threadIdx.x / N) * RL;
+        float win[WL];
+#pragma unroll
+        for (int i = 0; i < WL; ++i) {
+          const int off = i - kSlideHalf;
+          win[i] = (off >= -h && off < RL + h) ? t1p[y * S1 + wrap(x0 + off, N)] : 0.f;
+        }
+        float gv[RL];
+#pragma unroll
+        for (int i = 0; i < RL; ++i) gv[i] = sgx[0] * win[i + kSlideHalf];
+#pragma unroll
+        for (int dx = 1; dx <= kSlideHalf; ++dx) {
+          if (dx > h) break;
+          const float gd = sgx[dx];
+#pragma unroll
+          for (int i = 0; i < RL; ++i) gv[i] += gd * (win[i + kSlideHalf - dx] + win[i + kSlideHalf + dx]);
+        }
+#pragma unroll
+        for (int i = 0; i < RL; ++i) factor_at(y, x0 + i, gv[i], av[i]);
+      }
+    } else {
+      {
+        float gv[EP];
+#pragma unroll
+        for (int j = 0; j < EP; ++j) {
+          const int e = threadIdx.x + j * kThreads;
+          gv[j] = (NN % kThreads != 0 && e >= NN) ? 0.f : sgy[0] * t0[e];
+        }
+        for (int dy = 1; dy <= h; ++dy) {
+          const float gd = sgy[dy];
+#pragma unroll
+          for (int j = 0; j < EP; ++j) {
+            const int e = threadIdx.x + j * kThreads;
+            if (NN % kThreads != 0 && e >= NN) continue;
+            const int y = e / N, x = e - y * N;
+            gv[j] += gd * (t0[wrap(y - dy, N) * N + x] + t0[wrap(y + dy, N) * N + x]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < EP; ++j) {
+          const int e = threadIdx.x + j * kThreads;
+          if (NN % kThreads == 0 || e < NN) t1[e] = gv[j];
+        }
+      }
+      __syncthreads();
+      {
+        float gv[EP];
+#pragma unroll
+        for (int j = 0; j < EP; ++j) {
+          const int e = threadIdx.x + j * kThreads;
+          gv[j] = (NN % kThreads != 0 && e >= NN) ? 0.f : sgx[0] * t1[e];
+        }
+        for (int dx = 1; dx <= h; ++dx) {
+          const float gd = sgx[dx];
+#pragma unroll
+          for (int j = 0; j < EP; ++j) {
+            const int e = threadIdx.x + j * kThreads;
+            if (NN % kThreads != 0 && e >= NN) continue;
+            const int x = e % N;
+            const float* row = t1 + (e - x);
+            gv[j] += gd * (row[wrap(x - dx, N)] + row[wrap(x + dx, N)]);
+          }
+        }
 #pragma unroll
         for (int j = 0; j < EP; ++j) {
           const int e = threadIdx.x + j * kThreads;
           if (NN % kThreads != 0 && e >= NN) continue;
-          const int x = e % N;
-          const float* row = t1 + (e - x);
-          gv[j] += gd * (row[wrap(x - dx, N)] + row[wrap(x + dx, N)]);
+          factor_at(e / N, e % N, gv[j], av[j]);
         }
-      }
-#pragma unroll
-      for (int j = 0; j < EP; ++j) {
-        const int e = threadIdx.x + j * kThreads;
-        if (NN % kThreads != 0 && e >= NN) continue;
-        const float a = av[j];
-        float ag, f;
-        if (inten) {
-          ag = sqrtf(gv[j]);
-          f = a / sqrtf(gv[j] + p.eps * p.eps);
-        } else {
-          ag = gv[j];
-          f = a / (gv[j] + p.eps);
-        }
-        fbuf[e] = f;
-        const double dd = (double)a - (double)ag;
-        err += dd * dd;
       }
     }
     const double etot = block_sum_d(err, red);  // also: fbuf and the blur buffers are settled
@@ -221,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
       for_store_slots<N, N, false>([&](int s, int y, int x) { pvs[s] = k == 0 ? pi0[s] : pk[y * N + x]; });
       auto load_icol = [&](int s, int u, int y) {
         const float2 z = k == 0 ? psi0[y * N + u] : xk[y * N + u];
-        const float f = fbuf[y * N + u];
+        const float f = fbuf[y * S1 + u];
         return make_float2(z.x * f, z.y * f);  // no contraction anywhere in this file (fft_lds.hpp)
       };
       auto to_row = [&](int s, int u, int y, float2 z) { rowbuf[RowF::lidx(y, u)] = cscale(z, scale); };
@@ -255,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
     wmax = block_max_f(wmax, redf);
     const bool cc = (flags & FLAG_CC) != 0;
     float sa = 0.f, sp = 0.f;
-    float2 onew[SR];
+    float lna_s[SR], phi_s[SR];  // ln A and phi of the updated box, reused by Eq. (9)-(10)
     for_store_slots<N, N, false>([&](int s, int y, int x) {
       const int e = y * N + x;
       float2 o = obox[e];
@@ -266,10 +328,11 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
         o.y += sc * num[s].y;
         d.obj[(size_t)(rc.x + y) * W + rc.y + x] = o;
       }
-      onew[s] = o;
       if (cc) {
-        sa += fabsf(cc_ln_amp(o));
-        sp += fabsf(cc_phase(o));
+        lna_s[s] = cc_ln_amp(o);
+        phi_s[s] = cc_phase(o);
+        sa += fabsf(lna_s[s]);
+        sp += fabsf(phi_s[s]);
       }
     });
     if (cc) {
@@ -281,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_seq_iter(const CaseDesc* __restric
         const float inv_c = 1.0f / cbar;
         const float a1 = p.alpha1, a2 = p.alpha2;
         for_store_slots<N, N, false>([&](int s, int y, int x) {
-          d.obj[(size_t)(rc.x + y) * W + rc.y + x] = cc_apply(onew[s], cbar, inv_c, a1, a2);
+          d.obj[(size_t)(rc.x + y) * W + rc.y + x] = cc_apply_lp(lna_s[s], phi_s[s], cbar, inv_c, a1, a2);
         });
       }
     }
