@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
 // q in place; one data-error partial per row block.
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_factor(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
-  constexpr int L = Cfg<N>::ROWS;
+  constexpr int L = FactorRows<N>::R;
   constexpr int GX = N / L;
   constexpr int E = (L * N + kThreads - 1) / kThreads;
   __shared__ float tile[L * N];
@@ -1398,7 +1398,7 @@ int n_err_slots(int n, int v, int max_half) {
   switch (n) {
 #define PTY_CASE(N) \
   case N:           \
-    return N / Cfg<N>::ROWS;
+    return N / FactorRows<N>::R;
     PTY_FOR_EACH_N(PTY_CASE)
 #undef PTY_CASE
     default:
@@ -1471,7 +1471,7 @@ static hipError_t cols_fused_t(const CaseDesc* cases, const TableShape& t, int b
 }
 template <int N>
 static hipError_t factor_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  pty_launch(k_factor<N>, dim3((N / Cfg<N>::ROWS) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases,
+  pty_launch(k_factor<N>, dim3((N / FactorRows<N>::R) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases,
                      beta, it);
   return hipGetLastError();
 }

@@ -47,6 +47,14 @@ struct Cfg {
   static constexpr int COLS = largest_divisor_le(N, CCAP);
   static_assert(N % ROWS == 0 && N % COLS == 0, "tile must divide N");
 };
+// Rows per block of the modulus-factor pass: half a row-pass block, so that the
+// pass (whole rows, a short blur and the factor per element) launches twice the
+// workgroups and hides its latency with more waves.
+template <int N>
+struct FactorRows {
+  static constexpr int R = Cfg<N>::ROWS >= 2 ? Cfg<N>::ROWS / 2 : 1;
+  static_assert(N % R == 0, "row block must divide N");
+};
 template <int N, int V>
 struct ColW {
   static constexpr int W0 = V == 0 ? Cfg<N>::COLS / 2 : (V == 2 ? Cfg<N>::COLS * 2 : Cfg<N>::COLS);
