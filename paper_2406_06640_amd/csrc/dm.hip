@@ -184,6 +184,8 @@ __global__ __launch_bounds__(kThreads) void k_dm_wmax(const CaseDesc* __restrict
 __global__ __launch_bounds__(kThreads) void k_dm_obj(const CaseDesc* __restrict__ cases, const int* __restrict__ it) {
   __shared__ float red[kThreads / 64];
   __shared__ double2 redd[kThreads / 64];
+  __shared__ int s_pn[kThreads];
+  __shared__ int2 s_rc[kThreads];
   const CaseDesc* cs = cases + blockIdx.y;
   const DevParams& p = cs->p;
   const int tiles = tiles_of(p);
@@ -214,21 +216,55 @@ __global__ __launch_bounds__(kThreads) void k_dm_obj(const CaseDesc* __restrict_
     num[q] = make_float2(0.f, 0.f);
     mult[q] = 0;
   }
-  for (int i = lo; i < hi; ++i) {
-    const int pn = d.cov_pos[i];
-    const int2 rc = d.pos[pn];
-    const int xx = c0 + tx - rc.y;
-    const float2* ps = d.psi + (size_t)pn * K * nn;
+  // the tile's covering positions (ascending), staged in LDS a chunk at a time so that
+  // the gathers below wait on one load each; per pixel the terms are added in the
+  // order position, then mode
+  for (int c0i = lo; c0i < hi; c0i += kThreads) {
+    const int cn = min(kThreads, hi - c0i);
+    __syncthreads();  // the previous chunk is no longer read
+    if ((int)threadIdx.x < cn) {
+      const int pn = d.cov_pos[c0i + threadIdx.x];
+      s_pn[threadIdx.x] = pn;
+      s_rc[threadIdx.x] = d.pos[pn];
+    }
+    __syncthreads();
+    for (int i = 0; i < cn; ++i) {
+      const int pn = s_pn[i];
+      const int2 rc = s_rc[i];
+      const int xx = c0 + tx - rc.y;
+      const float2* ps = d.psi + (size_t)pn * K * nn;
+      bool in[kTilePix];
+      size_t e[kTilePix];
 #pragma unroll
-    for (int q = 0; q < kTilePix; ++q) {
-      const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
-      if (!((unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n)) continue;
-      const size_t e = (size_t)yy * n + xx;
-      w[q] += d.pw[e];
-      ++mult[q];
-      float2 acc = num[q];
-      for (int k = 0; k < K; ++k) acc = cadd(acc, cmulc(ps[(size_t)k * nn + e], d.probe[(size_t)k * nn + e]));
-      num[q] = acc;
+      for (int q = 0; q < kTilePix; ++q) {
+        const int yy = r0 + ty + q * kTileRowsPerPass - rc.x;
+        in[q] = (unsigned)yy < (unsigned)n && (unsigned)xx < (unsigned)n;
+        e[q] = in[q] ? (size_t)yy * n + xx : 0;
+        if (in[q]) {
+          w[q] += d.pw[e[q]];
+          ++mult[q];
+        }
+      }
+      int k = 0;
+      for (; k + 2 <= K; k += 2) {  // two modes' loads in flight
+        float2 a0[kTilePix], b0[kTilePix], a1[kTilePix], b1[kTilePix];
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q) {
+          if (!in[q]) continue;
+          a0[q] = ps[(size_t)k * nn + e[q]];
+          b0[q] = d.probe[(size_t)k * nn + e[q]];
+          a1[q] = ps[(size_t)(k + 1) * nn + e[q]];
+          b1[q] = d.probe[(size_t)(k + 1) * nn + e[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q)
+          if (in[q]) num[q] = cadd(cadd(num[q], cmulc(a0[q], b0[q])), cmulc(a1[q], b1[q]));
+      }
+      if (k < K) {
+#pragma unroll
+        for (int q = 0; q < kTilePix; ++q)
+          if (in[q]) num[q] = cadd(num[q], cmulc(ps[(size_t)k * nn + e[q]], d.probe[(size_t)k * nn + e[q]]));
+      }
     }
   }
   const float maxw = block_max_f(mw, red);
