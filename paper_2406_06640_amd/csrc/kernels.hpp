@@ -175,7 +175,7 @@ int dm_segments(int n_pos, int seg_len);
 // direction mode), the per-slot partial sums of the step normal equations, the
 // per-slot solves and their mean, and the update along the directions (k_obj_update
 // in apply mode, which also writes the complex constraint's sums).
-constexpr int kLsqChunk = 4096;  // frame pixels per block of the partial sums
+constexpr int kLsqChunk = 1024;  // frame pixels per block of the partial sums
 constexpr int kLsqTerms = 5;     // M11, M12, M22, r1, r2
 __host__ __device__ inline int lsq_chunks(int n) { return (n * n + kLsqChunk - 1) / kLsqChunk; }
 hipError_t launch_lsq_dir(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
