@@ -77,8 +77,35 @@ __device__ __forceinline__ void cmma(const CFrag& a, const CFrag& b, bool conj_b
 }
 
 // Row or column groups of 16 per workgroup: every table fragment a wave loads
-// serves kDftGroups groups (kDftGroups x 12 MFMAs per fragment load).
+// serves kDftGroups groups (kDftGroups x 12 MFMAs per fragment load).  The frame
+// operand is shared by the waves: for each 32-wide k-chunk, wave w loads and splits
+// group w's slice once and stages it in LDS (double-buffered), loading the next
+// chunk's slice while the current chunk's MFMAs run.
 constexpr int kDftGroups = 4;
+static_assert(kDftGroups == 256 / 64, "one staged group per wave");
+
+// LDS stage of one chunk: [group][plane rh, rl, ih, il][lane] fragments.
+struct DftStage {
+  bf16x8 f[kDftGroups][4][64];
+};
+__device__ __forceinline__ void dft_stage_put(DftStage& st, int g, int lane, const float2* v) {
+  float re[8], im[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    re[i] = v[i].x;
+    im[i] = v[i].y;
+  }
+  bf16x8 rh, rl, ih, il;
+  split8(re, rh, rl);
+  split8(im, ih, il);
+  st.f[g][0][lane] = rh;
+  st.f[g][1][lane] = rl;
+  st.f[g][2][lane] = ih;
+  st.f[g][3][lane] = il;
+}
+__device__ __forceinline__ CFrag dft_stage_get(const DftStage& st, int g, int lane) {
+  return CFrag{st.f[g][0][lane], st.f[g][1][lane], st.f[g][2][lane], st.f[g][3][lane]};
+}
 
 // Rows of every frame times F (or conj F): X[r][:] <- X[r][:] F, in place.
 // Block = kDftGroups x 16 rows; wave w produces output columns [w N/4, (w+1) N/4)
@@ -87,6 +114,7 @@ template <int N, bool INV>
 __global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows) {
   constexpr int TPW = N / 64;  // 16-column tiles per wave
   constexpr int G = kDftGroups;
+  __shared__ DftStage stage[2];
   const int r0 = blockIdx.x * 16 * G;
   if (r0 >= rows) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -99,33 +127,47 @@ __global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPl
       cr[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
       ci[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int kc = 0; kc < N; kc += 32) {
-    const int k0 = kc + kq * 8;
+  // this wave's rows: A[row][k] = X[r0 + 16 w + row][k]; B[k][col] = F[col][k] for the
+  // wave's columns w N/4 + 16 t + lr, chunk kb
+  auto load_b = [&](int kb, int t) {
+    const int rt = w * (N / 64) + t;
+    return CFrag{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
+                 F.frag(3, N, rt, kb, lane)};
+  };
+  CFrag b = load_b(0, 0);
+  const float2* xrow = X + (size_t)(r0 + w * 16 + lr) * N + kq * 8;
+  float2 nx[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) nx[i] = xrow[i];
+  dft_stage_put(stage[0], w, lane, nx);
+  __syncthreads();
+  for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
+    const int cur = it & 1;
+    const bool more = kc + 32 < N;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) nx[i] = xrow[kc + 32 + i];
+    }
     CFrag a[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const float2* xrow = X + (size_t)(r0 + g * 16 + lr) * N;
-      float re[8], im[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float2 v = xrow[k0 + i];
-        re[i] = v.x;
-        im[i] = v.y;
-      }
-      split8(re, a[g].rh, a[g].rl);
-      split8(im, a[g].ih, a[g].il);
-    }
+    for (int g = 0; g < G; ++g) a[g] = dft_stage_get(stage[cur], g, lane);
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      // B[k][col] = F[col][k], col = w N/4 + 16 t + lr
-      const int rt = w * (N / 64) + t, kb = kc / 32;
-      CFrag b{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
-              F.frag(3, N, rt, kb, lane)};
+      // the next table fragment (next tile, or the next chunk's first) loads during this tile's MFMAs
+      CFrag bn = b;
+      if (t + 1 < TPW)
+        bn = load_b(kc / 32, t + 1);
+      else if (more)
+        bn = load_b(kc / 32 + 1, 0);
 #pragma unroll
       for (int g = 0; g < G; ++g) cmma(a[g], b, INV, cr[g][t], ci[g][t]);
+      b = bn;
     }
+    if (more) dft_stage_put(stage[cur ^ 1], w, lane, nx);
+    // the next chunk is staged, and (after the last chunk) every wave has read the
+    // block's rows before any is overwritten
+    __syncthreads();
   }
-  __syncthreads();  // every wave has read the block's rows before any is overwritten
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -144,6 +186,7 @@ template <int N, bool INV>
 __global__ __launch_bounds__(256) void k_dft_left(float2* __restrict__ X, DftPlanes F, int frames) {
   constexpr int TPW = N / 64;
   constexpr int G = kDftGroups;
+  __shared__ DftStage stage[2];
   const int f = blockIdx.y;
   if (f >= frames) return;
   const int c0 = blockIdx.x * 16 * G;
@@ -158,36 +201,49 @@ __global__ __launch_bounds__(256) void k_dft_left(float2* __restrict__ X, DftPla
       cr[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
       ci[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int kc = 0; kc < N; kc += 32) {
-    const int k0 = kc + kq * 8;
+  // this wave's columns: B[k][col] = X[k][c0 + 16 w + col]; A[row][k] = F[row][k] for the
+  // wave's rows w N/4 + 16 t + lc, chunk kb
+  auto load_a = [&](int kb, int t) {
+    const int rt = w * (N / 64) + t;
+    return CFrag{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
+                 F.frag(3, N, rt, kb, lane)};
+  };
+  CFrag a = load_a(0, 0);
+  const float2* xcol = fr + (size_t)(kq * 8) * N + c0 + w * 16 + lc;
+  float2 nx[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) nx[i] = xcol[(size_t)i * N];
+  dft_stage_put(stage[0], w, lane, nx);
+  __syncthreads();
+  for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
+    const int cur = it & 1;
+    const bool more = kc + 32 < N;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) nx[i] = xcol[(size_t)(kc + 32 + i) * N];
+    }
     CFrag b[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      float re[8], im[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {  // B[k][col] = X[k][c0 + 16 g + col]
-        const float2 v = fr[(size_t)(k0 + i) * N + c0 + g * 16 + lc];
-        re[i] = v.x;
-        im[i] = v.y;
-      }
-      split8(re, b[g].rh, b[g].rl);
-      split8(im, b[g].ih, b[g].il);
-    }
+    for (int g = 0; g < G; ++g) b[g] = dft_stage_get(stage[cur], g, lane);
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      // A[row][k] = F[row][k], row = w N/4 + 16 t + lc
-      const int rt = w * (N / 64) + t, kb = kc / 32;
-      CFrag a{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
-              F.frag(3, N, rt, kb, lane)};
+      // the next table fragment (next tile, or the next chunk's first) loads during this tile's MFMAs
+      CFrag an = a;
+      if (t + 1 < TPW)
+        an = load_a(kc / 32, t + 1);
+      else if (more)
+        an = load_a(kc / 32 + 1, 0);
       if (INV) {  // conj(F) X: negate the imaginary part of the table operand
         a.ih = neg8(a.ih);
         a.il = neg8(a.il);
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) cmma(a, b[g], false, cr[g][t], ci[g][t]);
+      a = an;
     }
+    if (more) dft_stage_put(stage[cur ^ 1], w, lane, nx);
+    __syncthreads();
   }
-  __syncthreads();
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
