@@ -79,11 +79,20 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
     return gbs
 
 
-def per_slot_bytes(name, n, k, near=False):
+def paired_rows(n, batch):
+    """Whether the pc-ePIE batch passes run the paired inverse row pass (two slots per
+    workgroup, their probe contributions added on chip): power-of-two frames up to
+    512 and batches of at least 2, as the library selects it."""
+    return n & (n - 1) == 0 and n <= 512 and batch >= 2
+
+
+def per_slot_bytes(name, n, k, near=False, pairs=False):
     """HBM bytes one batch slot (one scan position) costs in kernel `name` as the kernels are
     built, counting each frame read or written at its pass boundary once (complex64 = 8 B,
-    float = 4 B).  Probe reads are shared by the batch and left out."""
+    float = 4 B).  Probe reads are shared by the batch and left out.  pairs: the inverse row
+    pass writes one probe-contribution frame set per pair of slots, which the update reads."""
     nn = n * n
+    xk = 4 * k if pairs else 8 * k  # probe-contribution frames per slot
     return {
         "fwd_rows": 16 * nn + 8 * k * nn,            # box gather in (exit waves and V), K frames out
         # K frames in (far field: not written back; near field: the transformed frames are stored),
@@ -92,16 +101,17 @@ def per_slot_bytes(name, n, k, near=False):
         "modulus_factor": 12 * nn,                   # blurred amplitude and measurement in, factor out
         "inv_cols": 16 * k * nn + 4 * nn,            # K row-transformed frames in, K frames out, factor in
         "cols_fused": 16 * k * nn + 4 * nn,          # K frames in and out, measurement in
-        "inv_rows_update": 16 * k * nn + 16 * nn,    # K frames in and out, box in, object numerator out
-        "obj_probe_update": 8 * k * nn + 12 * nn,   # K probe contributions in; object numerator and W gather in
+        # K frames in, probe contributions out, box in, object numerator out
+        "inv_rows_update": 8 * k * nn + xk * nn + 16 * nn,
+        "obj_probe_update": xk * nn + 12 * nn,       # probe contributions in; object numerator and W gather in
     }.get(name)
 
 
-def implementation_traffic(n, k, n_pos, ms_per_step, near=False):
+def implementation_traffic(n, k, n_pos, ms_per_step, near=False, pairs=False):
     """HBM bytes of a whole iteration as the kernels move them (per_slot_bytes of every batch
     pass x positions) against the measured step time: the average rate over all kernels."""
     classes = ("fwd_rows", "fwd_cols", "modulus_factor", "inv_cols", "inv_rows_update", "obj_probe_update")
-    total = sum(per_slot_bytes(c, n, k, near) for c in classes) * n_pos
+    total = sum(per_slot_bytes(c, n, k, near, pairs) for c in classes) * n_pos
     gbs = total / (ms_per_step * 1e-3) / 1e9
     return {"bytes": int(total), "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
@@ -371,7 +381,8 @@ def timed_leg(P, torch, s, cp, steps, warmup, copy_gbs, near, variant=None):
     n, k, n_pos = s["n"], s["k"], len(s["positions"])
     ms_per_step = 1e3 * wall / steps
     roof = None
-    pb = per_slot_bytes(dom, n, k, near)
+    pairs = paired_rows(n, cp.batch)
+    pb = per_slot_bytes(dom, n, k, near, pairs)
     if pb is not None and dom_cnt:
         # every launch of a batch kernel processes one full batch except the ragged last one
         launches_per_iter = -(-n_pos // cp.batch)
@@ -387,7 +398,7 @@ def timed_leg(P, torch, s, cp, steps, warmup, copy_gbs, near, variant=None):
     model = pass_model(n, k, near, s["positions"], order, cp.batch)
     return {"value": n_pos * k * steps / wall, "ms_per_step": ms_per_step, "roofline": roof,
             "graded": graded(model, ms_per_step, copy_gbs),
-            "implementation_traffic": implementation_traffic(n, k, n_pos, ms_per_step, near),
+            "implementation_traffic": implementation_traffic(n, k, n_pos, ms_per_step, near, pairs),
             "kernel_ms_per_step": {nm: round(ms, 4) for nm, (ms, c) in prof.items() if c},
             "column_tile_variant": variant, "final_data_error": float(errs[-1])}
 

@@ -35,6 +35,10 @@ __host__ __device__ __forceinline__ float2 conjc(float2 a) { return make_float2(
 __host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// The thread's index within its 256-thread group: a workgroup of 512 threads runs
+// two independent transforms, one per half, each on its own LDS buffer (every
+// synchronisation is still workgroup-wide, so both halves take the same path).
+__device__ __forceinline__ int fft_tid() { return threadIdx.x & 255; }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
 __host__ __device__ __forceinline__ float2 mul_mi(float2 a) {
@@ -146,7 +150,7 @@ struct Dft<16, INV> {
 
 // One in-place Stockham stage over NL lines: every thread first gathers the
 // inputs of its butterflies into registers, the workgroup synchronises, then
-// the outputs are written back into the same buffer.  blockDim.x must be 256.
+// the outputs are written back into the same buffer.  256 threads per transform.
 template <int N, int NL, int R, int NS, bool INV>
 __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf, int ld, const float2* __restrict__ tw) {
   constexpr int M = N / R;
@@ -155,7 +159,7 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf, int ld,
   float2 v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       const int line = f / M;
       const int j = f - line * M;
@@ -167,7 +171,7 @@ __device__ __forceinline__ void stockham_stage(float2* __restrict__ buf, int ld,
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       const int line = f / M;
       const int j = f - line * M;
@@ -270,7 +274,7 @@ __device__ __forceinline__ void mid_stage(float2* buf, const float2* __restrict_
   float2 v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       int line, j;
       F::template map<M>(f, line, j);
@@ -281,7 +285,7 @@ __device__ __forceinline__ void mid_stage(float2* buf, const float2* __restrict_
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       int line, j;
       F::template map<M>(f, line, j);
@@ -312,7 +316,7 @@ __device__ __forceinline__ void last_stage(float2* buf, const float2* __restrict
   float2 v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       int line, j;
       F::template map<M>(f, line, j);
@@ -323,7 +327,7 @@ __device__ __forceinline__ void last_stage(float2* buf, const float2* __restrict
   if (STORE_LDS) __syncthreads();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       int line, j;
       F::template map<M>(f, line, j);
@@ -409,7 +413,7 @@ __device__ __forceinline__ void for_slots(Fn&& fn) {
   constexpr int NB = (TOT + 255) / 256;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       int line, j;
       F::template map<M>(f, line, j);
@@ -446,7 +450,7 @@ __device__ __forceinline__ void fft_first(float2* v, float2* buf) {
   if (LOAD_LDS) __syncthreads();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int f = threadIdx.x + i * 256;
+    const int f = fft_tid() + i * 256;
     if (TOT % 256 == 0 || f < TOT) {
       Dft<R0, INV>::run(v + i * R0);
       if constexpr (!RegShape<N, NL>::SINGLE) {

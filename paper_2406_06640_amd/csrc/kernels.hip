@@ -187,6 +187,125 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(const CaseDesc* __restric
   for_store_slots<N, L, false>([&](int s, int line, int pos) { dO[line * N + pos] = acc[s]; });
 }
 
+// The inverse row pass over two slots per workgroup of 512 threads, one slot per
+// 256-thread half (LDS: a transform buffer per half and one exchange buffer).
+// Same transforms and epilogue as k_inv_rows, except that the probe numerator
+// contributions of the pair are added on chip: frame k of slot 2m receives
+// conj(o_2m) dpsi_2m,k + conj(o_2m+1) dpsi_2m+1,k (the second half hands its values
+// over through LDS) and the frames of slot 2m + 1 are left as they are, which
+// halves the contribution frames this pass writes and the probe update reads.
+// Without a slot 2m + 1 (the last pair of an odd batch) the second half
+// transforms slot 2m again and discards the result, so that both halves pass the
+// same synchronisations.
+template <int N, int NL, int SS>
+struct InvRowsPairStore {
+  float2* fr;
+  const float2* pk;
+  const float2* ov;
+  float2* dbgp;
+  float2* acc;
+  float2* xch;  // [SS][256]
+  float scale;
+  bool second, has_second;
+  float2 pv[SS];
+  float2 xv[SS];
+  __device__ __forceinline__ void pre(int s, int line, int pos) { pv[s] = pk[line * N + pos]; }
+  __device__ __forceinline__ void operator()(int s, int line, int pos, float2 v) {
+    const float2 psi_new = cscale(v, scale);
+    const float2 dpsi = csub(psi_new, cmul(ov[s], pv[s]));
+    acc[s] = cadd(acc[s], cmulc(dpsi, pv[s]));  // conj(P) dpsi
+    xv[s] = cmulc(dpsi, ov[s]);                 // conj(o) dpsi
+    if (dbgp) dbgp[line * N + pos] = psi_new;
+  }
+  __device__ __forceinline__ void post() {
+    const int t = fft_tid();
+    if (second) for_store_slots<N, NL, false>([&](int s, int, int) { xch[s * 256 + t] = xv[s]; });
+    __syncthreads();
+    if (!second)
+      for_store_slots<N, NL, false>([&](int s, int line, int pos) {
+        fr[line * N + pos] = has_second ? cadd(xv[s], xch[s * 256 + t]) : xv[s];
+      });
+  }
+};
+
+// Frame sizes with a paired inverse row pass: the power-of-two sizes up to 512,
+// whose pair kernels fit 256 registers per thread without spilling (the
+// radix-3 plans and N = 1024 keep one slot per workgroup).
+template <int N>
+struct PairRows {
+  static constexpr bool value = (N & (N - 1)) == 0 && N <= 512;
+};
+
+template <int N>
+constexpr size_t inv_rows_pair_lds() {
+  return sizeof(float2) *
+         (2 * N + 2 * Frame<N, Cfg<N>::ROWS, false>::ELEMS + RegShape<N, Cfg<N>::ROWS>::STORE_SLOTS * 256);
+}
+
+template <int N, bool NEAR>
+__global__ __launch_bounds__(2 * kThreads) void k_inv_rows_pair(const CaseDesc* __restrict__ cases, int beta,
+                                                                const int* __restrict__ it) {
+  constexpr int L = Cfg<N>::ROWS;
+  constexpr int SS = RegShape<N, L>::STORE_SLOTS;
+  constexpr int GX = N / L;
+  constexpr int EL = Frame<N, L, false>::ELEMS;
+  extern __shared__ float2 sm[];
+  Batch bt;
+  if (!open_batch(cases, beta, it, bt)) return;
+  const int b0 = 2 * (blockIdx.x / GX), bx = blockIdx.x % GX;
+  if (b0 >= bt.ns) return;
+  const bool second = threadIdx.x >= kThreads;
+  const bool has_second = b0 + 1 < bt.ns;
+  const bool real = !second || has_second;
+  const int b = (second && has_second) ? b0 + 1 : b0;
+  const DevParams& p = bt.cs->p;
+  const DevBufsG d = global_bufs(bt.cs->d);
+  const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
+  float2* tw = sm;
+  float2* hn = sm + N;
+  float2* buf = sm + 2 * N + (second ? EL : 0);
+  float2* xch = sm + 2 * N + 2 * EL;
+  const int y0 = bx * L;
+  const int2 rc = d.pos[bt.slots[b]];
+  for (int i = threadIdx.x; i < N; i += 2 * kThreads) {
+    tw[i] = d.tw[i];
+    if (NEAR) hn[i] = d.hnear[i];
+  }
+  const int K = p.k, W = p.w_obj;
+  float2 acc[SS];
+  const float2* orow = d.obj + (size_t)(rc.x + y0) * W + rc.y;
+#pragma unroll
+  for (int i = 0; i < SS; ++i) acc[i] = make_float2(0.f, 0.f);
+  float2 ob[SS];
+  for_store_slots<N, L, false>([&](int s, int line, int pos) { ob[s] = orow[line * W + pos]; });
+  const float scale = NEAR ? 1.0f / N : rsqrtf((float)N);
+  float2* x0 = d.X + ((size_t)b * K * N + y0) * N;
+  const float2* p0 = d.probe + (size_t)y0 * N;
+  float2* dbg0 = (dbg.psi_new && real) ? dbg.psi_new + ((size_t)b * K * N + y0) * N : nullptr;
+  auto gather = [&](int k, float2* v) {
+    const float2* fr = x0 + (size_t)k * N * N;
+    auto load = [&](int s, int line, int pos) { return fr[line * N + pos]; };
+    fft_gather<N, L, false>(v, load);
+  };
+  auto store_for = [&](int k) {
+    InvRowsPairStore<N, L, SS> st;
+    st.fr = x0 + (size_t)k * N * N;  // written by the first half only (slot 2m)
+    st.pk = p0 + (size_t)k * N * N;
+    st.ov = ob;
+    st.dbgp = dbg0 ? dbg0 + (size_t)k * N * N : nullptr;
+    st.acc = acc;
+    st.xch = xch;
+    st.scale = scale;
+    st.second = second;
+    st.has_second = has_second;
+    return st;
+  };
+  mode_loop<N, L, false, true, NEAR, true>(K, buf, tw, hn, gather, store_for);
+  if (!real) return;
+  float2* dO = d.dO + ((size_t)b * N + y0) * N;
+  for_store_slots<N, L, false>([&](int s, int line, int pos) { dO[line * N + pos] = acc[s]; });
+}
+
 // ---------------------------------------------------------------------------
 // Column passes (lines along y; Frame<N, C, true>: adjacent threads take
 // adjacent columns, so every global access is a coalesced row segment)
@@ -701,16 +820,18 @@ __host__ __device__ __forceinline__ int post_probe_blocks(int n, int k) {
 constexpr int kObjEpie = 0, kObjLsqDir = 1, kObjLsqApply = 2;
 
 // Probe side of one block of probe pixels.  kObjEpie and kObjLsqDir: numerator
-// N_P,k = sum_b X[b][k] (a fixed order: four interleaved partial sums over the
-// slots, combined pairwise) over the denominator (1-g) V + g max V; kObjEpie adds
+// N_P,k = sum of the contribution frames X[b][k] over b = 0, xstep, 2 xstep, ... < ns
+// (xstep 1: one frame per slot; 2: the paired inverse row pass left the sums of
+// slots b and b + 1 in frame b), in a fixed order: four interleaved partial sums
+// over the frames, combined pairwise; over the denominator (1-g) V + g max V; kObjEpie adds
 // probe_step times it to P_k, kObjLsqDir stores it as dP_k with sum_k conj(P_k) dP_k
 // and sum_k |dP_k|^2 per pixel.  kObjLsqApply: P_k += probe_step b dP_k.  The
 // updating modes write sum_k |P_k|^2 into the probe-power copy that the next batch
 // reads.
 template <int MODE>
 __device__ __forceinline__ void probe_update_block(const DevParams& p, const DevBufsG& d, const Batch& bt, int beta,
-                                                   float* pk2, float* red) {
-  const int n = p.n, K = p.k, ns = bt.ns;
+                                                   int xstep, float* pk2, float* red) {
+  const int n = p.n, K = p.k, nf = (bt.ns + xstep - 1) / xstep;
   const size_t nn = (size_t)n * n;
   float* pw_next = d.pw + (size_t)(pw_copy(bt.flags, beta) ^ 1) * nn;
   const int px_per = kThreads / pow2_at_least(K);
@@ -734,20 +855,20 @@ __device__ __forceinline__ void probe_update_block(const DevParams& p, const Dev
   if (act && MODE != kObjLsqApply) {
     // n is even, so a pixel pair never straddles the frame end and is 16-byte aligned
     const float4* x = reinterpret_cast<const float4*>(d.X + (size_t)k * nn + pix);
-    const size_t st = (size_t)K * nn / kPostPx;
+    const size_t st = (size_t)xstep * K * nn / kPostPx;
     auto add = [&](float2* acc, const float4& w) {
       acc[0] = cadd(acc[0], make_float2(w.x, w.y));
       acc[1] = cadd(acc[1], make_float2(w.z, w.w));
     };
     int b = 0;
-    for (; b + kPostUnroll <= ns; b += kPostUnroll) {
+    for (; b + kPostUnroll <= nf; b += kPostUnroll) {
       float4 w[kPostUnroll];
 #pragma unroll
       for (int u = 0; u < kPostUnroll; ++u) w[u] = x[(size_t)(b + u) * st];
 #pragma unroll
       for (int u = 0; u < kPostUnroll; ++u) add(s[u], w[u]);
     }
-    for (; b < ns; ++b) add(s[0], x[(size_t)b * st]);
+    for (; b < nf; ++b) add(s[0], x[(size_t)b * st]);
   }
   const float maxv = (MODE != kObjLsqApply) ? block_max_f(mv, red) : 0.f;
   const float bstep = (MODE == kObjLsqApply) ? p.probe_step * d.lsq_ab[1] : 0.f;
@@ -828,7 +949,8 @@ __device__ __forceinline__ void probe_update_block(const DevParams& p, const Dev
 // updating modes also write the tile's share of the C-bar sums of Eq. (11), each
 // pixel counted once per box that covers it, and the tile's coverage bitmasks.
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it) {
+__global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restrict__ cases, int beta, const int* __restrict__ it,
+                                                         int xstep) {
   __shared__ TileList tl;
   __shared__ float red[kThreads / 64];
   __shared__ double2 redd[kThreads / 64];
@@ -840,7 +962,7 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
   const DebugPtrsG dbg = global_dbg(bt.cs->dbg);
   const int pb = (bt.flags & FLAG_PROBE) ? post_probe_blocks(p.n, p.k) : 0;
   if ((int)blockIdx.x < pb) {
-    probe_update_block<MODE>(p, d, bt, beta, pk2, red);
+    probe_update_block<MODE>(p, d, bt, beta, xstep, pk2, red);
     return;
   }
   const int tiles = tiles_of(p), tiles_x = tiles_x_of(p);
@@ -982,7 +1104,9 @@ __global__ __launch_bounds__(kThreads) void k_obj_update(const CaseDesc* __restr
 // The complex constraint, Eq. (9)-(10), on kCcTiles object tiles per block: on
 // the tiles' pixels that lie in the union of the batch boxes (the coverage
 // bitmasks the object update wrote), with C-bar of Eq. (11) from the partial
-// sums the object update wrote (reduced once per block).  Every load is issued
+// sums the object update wrote (reduced once per block).  A block whose tiles
+// hold no covered pixel (most of the object, for one batch) leaves after reading
+// the bitmasks; the others fetch their covered pixels and the partial sums
 // before the C-bar reduction.  One tile per block: the transcendentals want
 // every wave the machine can hold (four tiles per block was measured slower).
 constexpr int kCcTiles = 1;
@@ -1001,18 +1125,29 @@ __global__ __launch_bounds__(kThreads) void k_constraint(const CaseDesc* __restr
   constexpr int PX = kCcTiles * kTilePix;
   unsigned rowm[PX];
   float2 ov[PX];
+  int any = 0;
 #pragma unroll
   for (int u = 0; u < kCcTiles; ++u) {
     const int tile = tile0 + u;
     const bool tv = tile < tiles;
-    const int r0 = (tile / tiles_x) * kObjTile, c = (tile % tiles_x) * kObjTile + tx;
 #pragma unroll
     for (int q = 0; q < kTilePix; ++q) {
       const int rr = ty + q * kTileRowsPerPass;
-      const int r = r0 + rr;
       rowm[u * kTilePix + q] = tv ? d.cov_mask[(size_t)tile * kObjTile + rr] : 0u;
-      ov[u * kTilePix + q] = (tv && r < p.h_obj && c < p.w_obj) ? d.obj[(size_t)r * p.w_obj + c]
-                                                               : make_float2(0.f, 0.f);
+      any |= (int)((rowm[u * kTilePix + q] >> tx) & 1u);
+    }
+  }
+  if (!__syncthreads_or(any)) return;
+  // a covered pixel lies inside the object (the bitmasks mark no other)
+#pragma unroll
+  for (int u = 0; u < kCcTiles; ++u) {
+    const int tile = tile0 + u;
+    const int r0 = (tile / tiles_x) * kObjTile, c = (tile % tiles_x) * kObjTile + tx;
+#pragma unroll
+    for (int q = 0; q < kTilePix; ++q) {
+      const int e = u * kTilePix + q;
+      const int r = r0 + ty + q * kTileRowsPerPass;
+      ov[e] = ((rowm[e] >> tx) & 1u) ? d.obj[(size_t)r * p.w_obj + c] : make_float2(0.f, 0.f);
     }
   }
   double sa = 0.0, sp = 0.0;
@@ -1438,10 +1573,51 @@ static hipError_t fwd_rows_t(const CaseDesc* cases, const TableShape& t, int bet
 template <int N, bool NEAR>
 static hipError_t inv_rows_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   constexpr int L = Cfg<N>::ROWS;
+  if constexpr (PairRows<N>::value) {
+    if (t.x_pairs) {
+      pty_launch(k_inv_rows_pair<N, NEAR>, dim3((N / L) * ((t.max_batch + 1) / 2), t.n_cases), dim3(2 * kThreads),
+                 inv_rows_pair_lds<N>(), s, cases, beta, it);
+      return hipGetLastError();
+    }
+  }
+  if (t.x_pairs) return hipErrorInvalidValue;  // a shape the runtime never builds
   const size_t sh = sizeof(float2) * (2 * N + Frame<N, L, false>::ELEMS);
   pty_launch(k_inv_rows<N, NEAR>, dim3((N / L) * t.max_batch, t.n_cases), dim3(kThreads), sh, s, cases,
                      beta, it);
   return hipGetLastError();
+}
+// The paired inverse row pass needs more than 64 KB of LDS per workgroup.
+template <int N>
+static hipError_t inv_rows_pair_attr() {
+  if constexpr (PairRows<N>::value) {
+    const int bytes = (int)inv_rows_pair_lds<N>();
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inv_rows_pair<N, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inv_rows_pair<N, true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  } else {
+    return hipSuccess;
+  }
+}
+bool inv_rows_paired(int n) {
+  switch (n) {
+#define PTY_CASE(N) \
+  case N:           \
+    return PairRows<N>::value;
+    PTY_FOR_EACH_N(PTY_CASE)
+#undef PTY_CASE
+    default:
+      return false;
+  }
+}
+hipError_t init_kernel_attributes() {
+  hipError_t e = hipSuccess;
+#define PTY_CASE_ATTR(N) \
+  if (e == hipSuccess) e = inv_rows_pair_attr<N>();
+  PTY_FOR_EACH_N(PTY_CASE_ATTR)
+#undef PTY_CASE_ATTR
+  return e;
 }
 template <int N, bool NEAR, int V>
 static hipError_t fwd_cols_v(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
@@ -1543,7 +1719,8 @@ PTY_DEFINE_LAUNCH(inv_cols)
 template <int MODE>
 static hipError_t obj_update_t(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   const int pb = post_probe_blocks(t.n, t.max_k);
-  pty_launch(k_obj_update<MODE>, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
+  pty_launch(k_obj_update<MODE>, dim3(pb + t.max_tiles, t.n_cases), dim3(kThreads), 0, s, cases, beta, it,
+             (MODE == kObjEpie && t.x_pairs) ? 2 : 1);
   return hipGetLastError();
 }
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {

@@ -114,6 +114,7 @@ struct TableShape {
   int col_variant;     // 0..kColVariants-1
   int max_half;        // max over cases of the blur half-width
   int max_dm_segments; // max over cases of the pc-DM probe-partial segments (0: no pc-DM case)
+  bool x_pairs;        // the inverse row pass adds the probe contributions of slot pairs
 };
 
 // Kernel classes (for timing).
@@ -142,6 +143,11 @@ hipError_t launch_factor(const CaseDesc* cases, const TableShape& t, int beta, c
 hipError_t launch_cols_fused(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_cols(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_inv_rows(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
+// Per-kernel launch attributes (LDS above 64 KB per workgroup); once per process
+// before the first launch.
+hipError_t init_kernel_attributes();
+// Whether frame size n has the paired inverse row pass (TableShape::x_pairs).
+bool inv_rows_paired(int n);
 hipError_t launch_obj_update(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_constraint(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 // Per-iteration launches.

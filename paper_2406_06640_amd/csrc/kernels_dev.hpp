@@ -240,12 +240,18 @@ template <class T, class = void>
 struct HasPre : std::false_type {};
 template <class T>
 struct HasPre<T, std::void_t<decltype(&T::pre)>> : std::true_type {};
+template <class T, class = void>
+struct HasPost : std::false_type {};
+template <class T>
+struct HasPost<T, std::void_t<decltype(&T::post)>> : std::true_type {};
 
 // One 1D pass over the K modes of a block's lines, with the next mode's inputs
 // gathered while the current mode is in its LDS stages.  gather(k, v) fills the
 // first-stage registers of mode k; store_for(k) returns the Store functor of mode
 // k.  NEAR: each pass is F^-1 h F (or F^-1 conj(h) F when CONJ), the transfer
-// function applied between the two transforms in LDS.
+// function applied between the two transforms in LDS.  A Store functor with a
+// post() member has it called by every thread once the mode's outputs are all
+// handed over (before the synchronisation that ends the mode).
 template <int N, int NL, bool LF, bool INV, bool NEAR, bool CONJ, class Gather, class StoreFor>
 __device__ __forceinline__ void mode_loop(int K, float2* buf, const float2* tw, const float2* hn, Gather& gather,
                                           StoreFor& store_for) {
@@ -276,6 +282,7 @@ __device__ __forceinline__ void mode_loop(int K, float2* buf, const float2* tw, 
       __syncthreads();
       fft_reg<N, NL, LF, true, true, false>(buf, tw, from_lds, store);
     }
+    if constexpr (HasPost<decltype(store)>::value) store.post();
     __syncthreads();
   }
 }

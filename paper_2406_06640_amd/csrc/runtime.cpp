@@ -447,6 +447,9 @@ TableShape single_shape(const ptycho_ctx* c, int max_batch) {
   sh.col_variant = c->col_variant;
   sh.max_half = c->dp.ks_half;
   sh.max_dm_segments = c->prm.engine == PTYCHO_ENGINE_DM ? dm_segments(c->prm.n_pos, c->dp.dm_seg_len) : 0;
+  // pc-LSQML's step sums read every slot's own probe contributions, and the dft_bf16
+  // path writes them per slot
+  sh.x_pairs = c->prm.engine == PTYCHO_ENGINE_EPIE && !c->prm.dft_bf16 && max_batch >= 2 && inv_rows_paired(sh.n);
   return sh;
 }
 
@@ -814,6 +817,10 @@ ptycho_status ptycho_init(const ptycho_params* params, const float* intensities,
   };
   if (hipGetDevice(&c->device) != hipSuccess) {
     c->err = "no HIP device";
+    return bail(PTYCHO_E_HIP);
+  }
+  if (hipError_t e = init_kernel_attributes(); e != hipSuccess) {
+    c->err = std::string("kernel attributes: ") + hipGetErrorString(e);
     return bail(PTYCHO_E_HIP);
   }
   {
@@ -1609,6 +1616,7 @@ ptycho_status ptycho_group_create(ptycho_ctx* const* ctxs, int32_t n, ptycho_gro
     TableShape& sh = tb.shape;
     sh.n_cases = (int)tb.members.size();
     sh.max_batch = std::max(sh.max_batch, c->prm.batch);
+    sh.x_pairs = sh.max_batch >= 2 && inv_rows_paired(sh.n);  // groups run the ePIE engine on the FFT path
     sh.max_tiles = std::max(sh.max_tiles, n_obj_tiles(c->dp));
     sh.max_k = std::max(sh.max_k, c->prm.n_modes);
     sh.max_side_jobs = std::max(sh.max_side_jobs, n_obj_tiles(c->dp) + n_probe_blocks(c->prm.n));
