@@ -58,36 +58,58 @@ struct DftPlanes {
   }
 };
 
-// Complex product of one 16 x 32 A fragment (split re/im) with one 32 x 16 B fragment.
-// conj_b: use conj(B).
+// Complex product of one 16 x 32 A fragment (split re/im) with one 32 x 16 B fragment,
+// conj_b: use conj(B); with the negated pair of A given, na = -(a.ih, a.il) (conj_b
+// false) or -(a.rh, a.rl) (conj_b true), so that no operand is negated per product:
+// (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br);  conj(b): bi -> -bi.
 struct CFrag {
   bf16x8 rh, rl, ih, il;
 };
-__device__ __forceinline__ void cmma(const CFrag& a, const CFrag& b, bool conj_b, floatx4& cr, floatx4& ci) {
-  // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br);  conj(b): bi -> -bi
+__device__ __forceinline__ void cmma_n(const CFrag& a, bf16x8 nah, bf16x8 nal, const CFrag& b, bool conj_b,
+                                       floatx4& cr, floatx4& ci) {
   cr = mma3(a.rh, a.rl, b.rh, b.rl, cr);
   if (!conj_b) {
-    cr = mma3(neg8(a.ih), neg8(a.il), b.ih, b.il, cr);
+    cr = mma3(nah, nal, b.ih, b.il, cr);
     ci = mma3(a.rh, a.rl, b.ih, b.il, ci);
   } else {
     cr = mma3(a.ih, a.il, b.ih, b.il, cr);
-    ci = mma3(neg8(a.rh), neg8(a.rl), b.ih, b.il, ci);
+    ci = mma3(nah, nal, b.ih, b.il, ci);
   }
   ci = mma3(a.ih, a.il, b.rh, b.rl, ci);
+}
+// A (F or conj F: conj_a) times B with the negated pair of B given, nb = -(b.ih, b.il)
+// (conj_a false) or -(b.rh, b.rl) (conj_a true).  The BF16 products are exact in FP32,
+// so a sign may sit on either operand of a product.
+__device__ __forceinline__ void cmma_bn(const CFrag& a, const CFrag& b, bf16x8 nbh, bf16x8 nbl, bool conj_a,
+                                        floatx4& cr, floatx4& ci) {
+  cr = mma3(a.rh, a.rl, b.rh, b.rl, cr);
+  if (!conj_a) {
+    cr = mma3(a.ih, a.il, nbh, nbl, cr);
+    ci = mma3(a.rh, a.rl, b.ih, b.il, ci);
+    ci = mma3(a.ih, a.il, b.rh, b.rl, ci);
+  } else {
+    cr = mma3(a.ih, a.il, b.ih, b.il, cr);
+    ci = mma3(a.rh, a.rl, b.ih, b.il, ci);
+    ci = mma3(a.ih, a.il, nbh, nbl, ci);
+  }
 }
 
 // Row or column groups of 16 per workgroup: every table fragment a wave loads
 // serves kDftGroups groups (kDftGroups x 12 MFMAs per fragment load).  The frame
-// operand is shared by the waves: for each 32-wide k-chunk, wave w loads and splits
-// group w's slice once and stages it in LDS (double-buffered), loading the next
-// chunk's slice while the current chunk's MFMAs run.
+// operand is shared by the W waves of the workgroup: for each 32-wide k-chunk, wave
+// w < kDftGroups loads and splits group w's slice once and stages it in LDS
+// (double-buffered), loading the next chunk's slice while the current chunk's MFMAs
+// run; the table fragments run two tiles ahead of the MFMAs.  W = 8 where N/16 splits
+// into 8 equal shares of output tiles (two waves per SIMD, 64 accumulator registers
+// each), else 4.
 constexpr int kDftGroups = 4;
-static_assert(kDftGroups == 256 / 64, "one staged group per wave");
 
-// LDS stage of one chunk: [group][plane rh, rl, ih, il][lane] fragments.
+// LDS stage of one chunk: [group][plane rh, rl, ih, il, then the negated pair the
+// complex product needs: -ih, -il or -rh, -rl][lane] fragments.
 struct DftStage {
-  bf16x8 f[kDftGroups][4][64];
+  bf16x8 f[kDftGroups][6][64];
 };
+template <bool NEG_RE>
 __device__ __forceinline__ void dft_stage_put(DftStage& st, int g, int lane, const float2* v) {
   float re[8], im[8];
 #pragma unroll
@@ -102,17 +124,20 @@ __device__ __forceinline__ void dft_stage_put(DftStage& st, int g, int lane, con
   st.f[g][1][lane] = rl;
   st.f[g][2][lane] = ih;
   st.f[g][3][lane] = il;
+  st.f[g][4][lane] = NEG_RE ? neg8(rh) : neg8(ih);
+  st.f[g][5][lane] = NEG_RE ? neg8(rl) : neg8(il);
 }
 __device__ __forceinline__ CFrag dft_stage_get(const DftStage& st, int g, int lane) {
   return CFrag{st.f[g][0][lane], st.f[g][1][lane], st.f[g][2][lane], st.f[g][3][lane]};
 }
 
 // Rows of every frame times F (or conj F): X[r][:] <- X[r][:] F, in place.
-// Block = kDftGroups x 16 rows; wave w produces output columns [w N/4, (w+1) N/4)
+// Block = kDftGroups x 16 rows; wave w produces output columns [w N/W, (w+1) N/W)
 // of every row group.
-template <int N, bool INV>
-__global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows) {
-  constexpr int TPW = N / 64;  // 16-column tiles per wave
+template <int N, bool INV, int W>
+__global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows) {
+  constexpr int TPW = N / (16 * W);  // 16-column tiles per wave
+  static_assert(W >= kDftGroups && TPW * 16 * W == N, "wave count");
   constexpr int G = kDftGroups;
   __shared__ DftStage stage[2];
   const int r0 = blockIdx.x * 16 * G;
@@ -127,43 +152,58 @@ __global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPl
       cr[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
       ci[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  // this wave's rows: A[row][k] = X[r0 + 16 w + row][k]; B[k][col] = F[col][k] for the
-  // wave's columns w N/4 + 16 t + lr, chunk kb
+  // A[row][k] = X[r0 + 16 g + row][k] per row group g; B[k][col] = F[col][k] for the
+  // wave's columns w N/W + 16 t + lr, chunk kb
   auto load_b = [&](int kb, int t) {
-    const int rt = w * (N / 64) + t;
+    const int rt = w * TPW + t;
     return CFrag{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
                  F.frag(3, N, rt, kb, lane)};
   };
-  CFrag b = load_b(0, 0);
-  const float2* xrow = X + (size_t)(r0 + w * 16 + lr) * N + kq * 8;
+  const bool stager = w < G;  // waves 0..G-1 stage one row group each
+  // table fragments run two tiles ahead: b (this tile), b1 (the next), loads for the one after
+  auto tile_at = [&](int kb, int t, CFrag& dst) {
+    while (t >= TPW) {  // TPW may be 1: two tiles ahead can be two chunks ahead
+      t -= TPW;
+      ++kb;
+    }
+    if (kb * 32 < N) dst = load_b(kb, t);
+  };
+  CFrag b = load_b(0, 0), b1 = b;
+  tile_at(0, 1, b1);
+  const float2* xrow = X + (size_t)(r0 + (stager ? w : 0) * 16 + lr) * N + kq * 8;
   float2 nx[8];
+  if (stager) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) nx[i] = xrow[i];
-  dft_stage_put(stage[0], w, lane, nx);
+    for (int i = 0; i < 8; ++i) nx[i] = xrow[i];
+    dft_stage_put<INV>(stage[0], w, lane, nx);
+  }
   __syncthreads();
   for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
     const int cur = it & 1;
     const bool more = kc + 32 < N;
-    if (more) {
+    if (more && stager) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) nx[i] = xrow[kc + 32 + i];
     }
     CFrag a[G];
+    bf16x8 na_h[G], na_l[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) a[g] = dft_stage_get(stage[cur], g, lane);
+    for (int g = 0; g < G; ++g) {
+      a[g] = dft_stage_get(stage[cur], g, lane);
+      na_h[g] = stage[cur].f[g][4][lane];
+      na_l[g] = stage[cur].f[g][5][lane];
+    }
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      // the next table fragment (next tile, or the next chunk's first) loads during this tile's MFMAs
-      CFrag bn = b;
-      if (t + 1 < TPW)
-        bn = load_b(kc / 32, t + 1);
-      else if (more)
-        bn = load_b(kc / 32 + 1, 0);
+      // the table fragment two tiles ahead loads during this tile's MFMAs
+      CFrag b2 = b1;
+      tile_at(kc / 32, t + 2, b2);
 #pragma unroll
-      for (int g = 0; g < G; ++g) cmma(a[g], b, INV, cr[g][t], ci[g][t]);
-      b = bn;
+      for (int g = 0; g < G; ++g) cmma_n(a[g], na_h[g], na_l[g], b, INV, cr[g][t], ci[g][t]);
+      b = b1;
+      b1 = b2;
     }
-    if (more) dft_stage_put(stage[cur ^ 1], w, lane, nx);
+    if (more && stager) dft_stage_put<INV>(stage[cur ^ 1], w, lane, nx);
     // the next chunk is staged, and (after the last chunk) every wave has read the
     // block's rows before any is overwritten
     __syncthreads();
@@ -172,7 +212,7 @@ __global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPl
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int col = w * (N / 4) + t * 16 + lr;
+      const int col = (w * TPW + t) * 16 + lr;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         X[(size_t)(r0 + g * 16 + kq * 4 + i) * N + col] = make_float2(cr[g][t][i], ci[g][t][i]);
@@ -181,10 +221,11 @@ __global__ __launch_bounds__(256) void k_dft_right(float2* __restrict__ X, DftPl
 
 // F (or conj F) times every column of each frame: X_f <- F X_f, in place.
 // Block = kDftGroups x 16 columns of one frame (blockIdx.y); wave w produces rows
-// [w N/4, (w+1) N/4) of every column group.
-template <int N, bool INV>
-__global__ __launch_bounds__(256) void k_dft_left(float2* __restrict__ X, DftPlanes F, int frames) {
-  constexpr int TPW = N / 64;
+// [w N/W, (w+1) N/W) of every column group.
+template <int N, bool INV, int W>
+__global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, DftPlanes F, int frames) {
+  constexpr int TPW = N / (16 * W);
+  static_assert(W >= kDftGroups && TPW * 16 * W == N, "wave count");
   constexpr int G = kDftGroups;
   __shared__ DftStage stage[2];
   const int f = blockIdx.y;
@@ -201,54 +242,65 @@ __global__ __launch_bounds__(256) void k_dft_left(float2* __restrict__ X, DftPla
       cr[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
       ci[g][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  // this wave's columns: B[k][col] = X[k][c0 + 16 w + col]; A[row][k] = F[row][k] for the
-  // wave's rows w N/4 + 16 t + lc, chunk kb
+  // B[k][col] = X[k][c0 + 16 g + col] per column group g; A[row][k] = F[row][k] for the
+  // wave's rows w N/W + 16 t + lc, chunk kb
   auto load_a = [&](int kb, int t) {
-    const int rt = w * (N / 64) + t;
+    const int rt = w * TPW + t;
     return CFrag{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
                  F.frag(3, N, rt, kb, lane)};
   };
-  CFrag a = load_a(0, 0);
-  const float2* xcol = fr + (size_t)(kq * 8) * N + c0 + w * 16 + lc;
+  // table fragments run two tiles ahead: a (this tile), a1 (the next), loads for the one after
+  auto tile_at = [&](int kb, int t, CFrag& dst) {
+    while (t >= TPW) {  // TPW may be 1: two tiles ahead can be two chunks ahead
+      t -= TPW;
+      ++kb;
+    }
+    if (kb * 32 < N) dst = load_a(kb, t);
+  };
+  CFrag a = load_a(0, 0), a1 = a;
+  tile_at(0, 1, a1);
+  const bool stager = w < G;  // waves 0..G-1 stage one column group each
+  const float2* xcol = fr + (size_t)(kq * 8) * N + c0 + (stager ? w : 0) * 16 + lc;
   float2 nx[8];
+  if (stager) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) nx[i] = xcol[(size_t)i * N];
-  dft_stage_put(stage[0], w, lane, nx);
+    for (int i = 0; i < 8; ++i) nx[i] = xcol[(size_t)i * N];
+    dft_stage_put<INV>(stage[0], w, lane, nx);
+  }
   __syncthreads();
   for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
     const int cur = it & 1;
     const bool more = kc + 32 < N;
-    if (more) {
+    if (more && stager) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) nx[i] = xcol[(size_t)(kc + 32 + i) * N];
     }
     CFrag b[G];
+    bf16x8 nb_h[G], nb_l[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) b[g] = dft_stage_get(stage[cur], g, lane);
+    for (int g = 0; g < G; ++g) {
+      b[g] = dft_stage_get(stage[cur], g, lane);
+      nb_h[g] = stage[cur].f[g][4][lane];
+      nb_l[g] = stage[cur].f[g][5][lane];
+    }
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      // the next table fragment (next tile, or the next chunk's first) loads during this tile's MFMAs
-      CFrag an = a;
-      if (t + 1 < TPW)
-        an = load_a(kc / 32, t + 1);
-      else if (more)
-        an = load_a(kc / 32 + 1, 0);
-      if (INV) {  // conj(F) X: negate the imaginary part of the table operand
-        a.ih = neg8(a.ih);
-        a.il = neg8(a.il);
-      }
+      // the table fragment two tiles ahead loads during this tile's MFMAs
+      CFrag a2 = a1;
+      tile_at(kc / 32, t + 2, a2);
 #pragma unroll
-      for (int g = 0; g < G; ++g) cmma(a, b[g], false, cr[g][t], ci[g][t]);
-      a = an;
+      for (int g = 0; g < G; ++g) cmma_bn(a, b[g], nb_h[g], nb_l[g], INV, cr[g][t], ci[g][t]);
+      a = a1;
+      a1 = a2;
     }
-    if (more) dft_stage_put(stage[cur ^ 1], w, lane, nx);
+    if (more && stager) dft_stage_put<INV>(stage[cur ^ 1], w, lane, nx);
     __syncthreads();
   }
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int row0 = w * (N / 4) + t * 16 + kq * 4;
+      const int row0 = (w * TPW + t) * 16 + kq * 4;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         fr[(size_t)(row0 + i) * N + c0 + g * 16 + lc] = make_float2(cr[g][t][i], ci[g][t][i]);
@@ -406,14 +458,15 @@ int dft_err_slots(int n) { return (n / kDftTile) * (n / kDftTile); }
 template <int N>
 static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inverse, hipStream_t s) {
   static_assert(N % (16 * kDftGroups) == 0, "whole row / column groups per block");
+  constexpr int W = (N % 128 == 0) ? 8 : 4;  // two waves per SIMD where the tiles divide
   DftPlanes F{planes};
   const int rows = frames * N;
   if (!inverse) {
-    pty_launch(k_dft_right<N, false>, dim3(rows / (16 * kDftGroups)), dim3(256), 0, s, X, F, rows);
-    pty_launch(k_dft_left<N, false>, dim3(N / (16 * kDftGroups), frames), dim3(256), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, false, W>, dim3(rows / (16 * kDftGroups)), dim3(64 * W), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, false, W>, dim3(N / (16 * kDftGroups), frames), dim3(64 * W), 0, s, X, F, frames);
   } else {
-    pty_launch(k_dft_left<N, true>, dim3(N / (16 * kDftGroups), frames), dim3(256), 0, s, X, F, frames);
-    pty_launch(k_dft_right<N, true>, dim3(rows / (16 * kDftGroups)), dim3(256), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, true, W>, dim3(N / (16 * kDftGroups), frames), dim3(64 * W), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, true, W>, dim3(rows / (16 * kDftGroups)), dim3(64 * W), 0, s, X, F, rows);
   }
   return hipGetLastError();
 }
