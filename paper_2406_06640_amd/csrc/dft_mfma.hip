@@ -322,7 +322,14 @@ __global__ __launch_bounds__(kThreads) void k_dft_exit(const CaseDesc* __restric
   const int2 rc = d.pos[bt.slots[b]];
   const int y = pix / n, x = pix - y * n;
   const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
-  for (int k = 0; k < K; ++k) d.X[((size_t)b * K + k) * nn + pix] = cmul(o, d.probe[(size_t)k * nn + pix]);
+  // mode k + 1's probe value is loaded before mode k's store (a load behind a store
+  // would wait for it)
+  float2 pv = d.probe[pix];
+  for (int k = 0; k < K; ++k) {
+    const float2 pn = k + 1 < K ? d.probe[(size_t)(k + 1) * nn + pix] : pv;
+    d.X[((size_t)b * K + k) * nn + pix] = cmul(o, pv);
+    pv = pn;
+  }
 }
 
 // Side work of the batch (see side_job) as its own launch.
@@ -392,27 +399,44 @@ __global__ __launch_bounds__(kThreads) void k_dft_blur_apply(const CaseDesc* __r
   const float* amp = d.amp + (size_t)pat * nn;
   float* dbgf = bt.cs->dbg.factor ? bt.cs->dbg.factor + (size_t)b * nn : nullptr;
   double err = 0.0;
-  for (int e = threadIdx.x; e < kDftTile * kDftTile; e += kThreads) {
+  // the thread's kPx pixels: factors first, then per mode the loads of all of them,
+  // with the next mode's loads issued before this mode's stores
+  constexpr int kPx = kDftTile * kDftTile / kThreads;
+  static_assert(kPx * kThreads == kDftTile * kDftTile, "whole pixels per thread");
+  size_t idx[kPx];
+  float f[kPx];
+#pragma unroll
+  for (int j = 0; j < kPx; ++j) {
+    const int e = threadIdx.x + j * kThreads;
     const int y = e / kDftTile, x = e - y * kDftTile;
     float g = p.gy[0] * hs[y + h][x];
     for (int dy = 1; dy <= h; ++dy) g += p.gy[dy] * (hs[y + h - dy][x] + hs[y + h + dy][x]);
-    const size_t idx = (size_t)(ty0 + y) * n + tx0 + x;
-    const float a = amp[idx];
-    float ag, f;
+    idx[j] = (size_t)(ty0 + y) * n + tx0 + x;
+    const float a = amp[idx[j]];
+    float ag;
     if (p.blur_intensity) {
       ag = sqrtf(g);
-      f = a / sqrtf(g + p.eps * p.eps);
+      f[j] = a / sqrtf(g + p.eps * p.eps);
     } else {
       ag = g;
-      f = a / (g + p.eps);
+      f[j] = a / (g + p.eps);
     }
-    if (dbgf) dbgf[idx] = f;
+    if (dbgf) dbgf[idx[j]] = f[j];
     const double dd = (double)a - (double)ag;
     err += dd * dd;
-    for (int k = 0; k < K; ++k) {
-      float2* xv = d.X + ((size_t)b * K + k) * nn + idx;
-      *xv = cscale(*xv, f);
-    }
+  }
+  float2* xb = d.X + (size_t)b * K * nn;
+  float2 cur[kPx];
+#pragma unroll
+  for (int j = 0; j < kPx; ++j) cur[j] = xb[idx[j]];
+  for (int k = 0; k < K; ++k) {
+    float2 nxt[kPx];
+#pragma unroll
+    for (int j = 0; j < kPx; ++j) nxt[j] = k + 1 < K ? xb[(size_t)(k + 1) * nn + idx[j]] : cur[j];
+#pragma unroll
+    for (int j = 0; j < kPx; ++j) xb[(size_t)k * nn + idx[j]] = cscale(cur[j], f[j]);
+#pragma unroll
+    for (int j = 0; j < kPx; ++j) cur[j] = nxt[j];
   }
   const double tot = block_sum_d(err, red);
   if (threadIdx.x == 0) d.err_part[(size_t)pat * tiles + tile] = tot;
@@ -436,14 +460,19 @@ __global__ __launch_bounds__(kThreads) void k_dft_delta(const CaseDesc* __restri
   const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
   float2* dbgp = bt.cs->dbg.psi_new;
   float2 acc = make_float2(0.f, 0.f);
+  // mode k + 1's inputs are loaded before mode k's stores
+  float2* xb = d.X + (size_t)b * K * nn + pix;
+  float2 psi_new = xb[0], pv = d.probe[pix];
   for (int k = 0; k < K; ++k) {
-    float2* xv = d.X + ((size_t)b * K + k) * nn + pix;
-    const float2 psi_new = *xv;
+    const bool more = k + 1 < K;
+    const float2 psi_n = more ? xb[(size_t)(k + 1) * nn] : psi_new;
+    const float2 pv_n = more ? d.probe[(size_t)(k + 1) * nn + pix] : pv;
     if (dbgp) dbgp[((size_t)b * K + k) * nn + pix] = psi_new;
-    const float2 pv = d.probe[(size_t)k * nn + pix];
     const float2 dpsi = csub(psi_new, cmul(o, pv));
     acc = cadd(acc, cmulc(dpsi, pv));
-    *xv = cmulc(dpsi, o);
+    xb[(size_t)k * nn] = cmulc(dpsi, o);
+    psi_new = psi_n;
+    pv = pv_n;
   }
   d.dO[(size_t)b * nn + pix] = acc;
 }
