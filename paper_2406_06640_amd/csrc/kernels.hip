@@ -365,20 +365,44 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(const CaseDesc* __restric
   float* tile = reinterpret_cast<float*>(buf);
   constexpr int TS = C + 1;
   const bool inten = p.blur_intensity != 0;
-  for_store_slots<N, C, true>([&](int s, int c, int y) { tile[y * TS + c] = inten ? acc[s] : sqrtf(acc[s]); });
-  __syncthreads();
   float* q = d.q + (size_t)b * N * N + x0;
   const int h = p.ks_half;
   const float* gy = sgy;
   // taps outermost for independent per-element chains (each element still adds
   // its taps in the order 0, 1, ..., h)
   float gv[SS];
-  for_store_slots<N, C, true>([&](int s, int c, int y) { gv[s] = gy[0] * tile[y * TS + c]; });
-  for (int dy = 1; dy <= h; ++dy) {
-    const float gd = gy[dy];
+  constexpr int H = kMaxHalf;
+  if constexpr (N >= 2 * H) {
+    // the column tile with kMaxHalf rows of periodic padding above and below (it fits
+    // the transform buffer from N = 2 kMaxHalf): every tap reads at a fixed offset
+    // from the element's row, no index wrap
     for_store_slots<N, C, true>([&](int s, int c, int y) {
-      gv[s] += gd * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
+      const float v = inten ? acc[s] : sqrtf(acc[s]);
+      tile[(y + H) * TS + c] = v;
+      if (y < H) tile[(y + N + H) * TS + c] = v;
+      if (y >= N - H) tile[(y - N + H) * TS + c] = v;
     });
+    __syncthreads();
+    for_store_slots<N, C, true>([&](int s, int c, int y) { gv[s] = gy[0] * tile[(y + H) * TS + c]; });
+#pragma unroll
+    for (int dy = 1; dy <= H; ++dy) {
+      if (dy <= h) {  // uniform: the taps beyond the kernel's half-width are skipped
+        const float gd = gy[dy];
+        for_store_slots<N, C, true>([&](int s, int c, int y) {
+          gv[s] += gd * (tile[(y + H - dy) * TS + c] + tile[(y + H + dy) * TS + c]);
+        });
+      }
+    }
+  } else {
+    for_store_slots<N, C, true>([&](int s, int c, int y) { tile[y * TS + c] = inten ? acc[s] : sqrtf(acc[s]); });
+    __syncthreads();
+    for_store_slots<N, C, true>([&](int s, int c, int y) { gv[s] = gy[0] * tile[y * TS + c]; });
+    for (int dy = 1; dy <= h; ++dy) {
+      const float gd = gy[dy];
+      for_store_slots<N, C, true>([&](int s, int c, int y) {
+        gv[s] += gd * (tile[wrap(y - dy, N) * TS + c] + tile[wrap(y + dy, N) * TS + c]);
+      });
+    }
   }
   for_store_slots<N, C, true>([&](int s, int c, int y) { q[y * N + c] = gv[s]; });
 }
