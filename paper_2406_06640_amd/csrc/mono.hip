@@ -83,6 +83,25 @@ constexpr int kMonoQ = kMonoTy / (kThreads / 64);  // output rows per thread
 __host__ __device__ inline int mono_tiles(int n) {
   return ((n + kMonoTx - 1) / kMonoTx) * ((n + kMonoTy - 1) / kMonoTy);
 }
+// dst[i] = ld(i) for i < cnt over the block's threads, kB loads of a thread in
+// flight before its LDS stores (instead of one global round trip per value).
+template <int kB, class Ld>
+__device__ __forceinline__ void lds_fill(float* dst, int cnt, Ld ld) {
+  for (int i0 = threadIdx.x; i0 < cnt; i0 += kB * kThreads) {
+    float v[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int i = i0 + j * kThreads;
+      v[j] = i < cnt ? ld(i) : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int i = i0 + j * kThreads;
+      if (i < cnt) dst[i] = v[j];
+    }
+  }
+}
+
 // Dynamic LDS of k_mono_apply: region, slice indices and samples (or counts), and
 // for the adjoint with few taps the slice's weights.
 __host__ __device__ inline size_t mono_lds_bytes(int count, int stride, bool adj_w) {
@@ -248,13 +267,13 @@ __global__ __launch_bounds__(kThreads) void k_mono_apply(const float* __restrict
     }
   }
   if (ADJ && TAPS > 0) {
-    for (int i = threadIdx.x; i < sp.count * kMonoSl * st; i += kThreads) {
+    lds_fill<8>(sw, sp.count * kMonoSl * st, [&](int i) {
       const int e = i / st, w = i % st;
       const int j = e / kMonoSl, k = e % kMonoSl;
       const bool ok = k < kMonoTx ? k < lx : k - kMonoTx < ly;
       const int u = k < kMonoTx ? x0 + k : y0 + k - kMonoTx;
-      sw[i] = ok ? tb.adj_w[((size_t)j * n + u) * st + w] : 0.f;
-    }
+      return ok ? tb.adj_w[((size_t)j * n + u) * st + w] : 0.f;
+    });
   }
   __syncthreads();
   // the spans clamped to the frame: samples outside it read zero
@@ -264,9 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_mono_apply(const float* __restrict
   sx = make_int2(max(sx.x, 0), min(sx.y, n - 1));
   const int rh = sy.y - sy.x + 1, rw = sx.y - sx.x + 1;
   const bool staged = rh > 0 && rw > 0 && rh * rw <= kMonoLds;
-  if (staged) {
-    for (int i = threadIdx.x; i < rh * rw; i += kThreads) reg[i] = m[(size_t)(sy.x + i / rw) * n + sx.x + i % rw];
-  }
+  if (staged) lds_fill<8>(reg, rh * rw, [&](int i) { return m[(size_t)(sy.x + i / rw) * n + sx.x + i % rw]; });
   __syncthreads();
   float* op = out + (size_t)pat * nn;
   const float ss = staged ? mono_outputs<ADJ, TAPS, true>(m, reg, sy.x, sx.x, rw, n, sp, tb, x0, y0, sa, stt, sc, sw, op)
