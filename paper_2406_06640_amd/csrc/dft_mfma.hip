@@ -133,9 +133,13 @@ __device__ __forceinline__ CFrag dft_stage_get(const DftStage& st, int g, int la
 
 // Rows of every frame times F (or conj F): X[r][:] <- X[r][:] F, in place.
 // Block = kDftGroups x 16 rows; wave w produces output columns [w N/W, (w+1) N/W)
-// of every row group.
-template <int N, bool INV, int W>
-__global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows) {
+// of every row group.  EXIT: the frames are the exit waves of batch `beta` (frame
+// f = b K + k holds o_b P_k), formed while staging instead of read from X (which
+// receives the transformed rows); the workgroup's 64 rows lie in one frame.
+template <int N, bool INV, int W, bool EXIT>
+__global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, DftPlanes F, int rows,
+                                                      const CaseDesc* __restrict__ cases, int beta,
+                                                      const int* __restrict__ it) {
   constexpr int TPW = N / (16 * W);  // 16-column tiles per wave
   static_assert(W >= kDftGroups && TPW * 16 * W == N, "wave count");
   constexpr int G = kDftGroups;
@@ -170,21 +174,47 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
   };
   CFrag b = load_b(0, 0), b1 = b;
   tile_at(0, 1, b1);
-  const float2* xrow = X + (size_t)(r0 + (stager ? w : 0) * 16 + lr) * N + kq * 8;
+  const int srow = r0 + (stager ? w : 0) * 16 + lr;  // the row this lane stages
+  const float2* xrow = X + (size_t)srow * N + kq * 8;
+  // EXIT: this lane's row of o_b and of P_k (b, k from the frame of row srow)
+  const float2* orow = nullptr;
+  const float2* prow = nullptr;
+  if constexpr (EXIT) {
+    Batch bt;
+    if (!open_batch(cases, beta, it, bt)) return;  // uniform: every thread leaves
+    const DevParams& p = bt.cs->p;
+    const DevBufsG d = global_bufs(bt.cs->d);
+    const int f = srow / N, y = srow % N;
+    const int b = f / p.k, k = f % p.k;
+    const int2 rc = d.pos[bt.slots[b]];
+    orow = d.obj + (size_t)(rc.x + y) * p.w_obj + rc.y + kq * 8;
+    prow = d.probe + ((size_t)k * N + y) * N + kq * 8;
+  }
+  auto load_chunk = [&](int kc, float2* v) {
+    if constexpr (EXIT) {
+      float2 ov[8], pv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        ov[i] = orow[kc + i];
+        pv[i] = prow[kc + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = cmul(ov[i], pv[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = xrow[kc + i];
+    }
+  };
   float2 nx[8];
   if (stager) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) nx[i] = xrow[i];
+    load_chunk(0, nx);
     dft_stage_put<INV>(stage[0], w, lane, nx);
   }
   __syncthreads();
   for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
     const int cur = it & 1;
     const bool more = kc + 32 < N;
-    if (more && stager) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) nx[i] = xrow[kc + 32 + i];
-    }
+    if (more && stager) load_chunk(kc + 32, nx);
     CFrag a[G];
     bf16x8 na_h[G], na_l[G];
 #pragma unroll
@@ -305,31 +335,6 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
       for (int i = 0; i < 4; ++i)
         fr[(size_t)(row0 + i) * N + c0 + g * 16 + lc] = make_float2(cr[g][t][i], ci[g][t][i]);
     }
-}
-
-// Exit waves of the batch into the work frames: X[b][k] = o_b P_k.
-__global__ __launch_bounds__(kThreads) void k_dft_exit(const CaseDesc* __restrict__ cases, int beta,
-                                                       const int* __restrict__ it) {
-  Batch bt;
-  if (!open_batch(cases, beta, it, bt)) return;
-  const DevParams& p = bt.cs->p;
-  const DevBufsG d = global_bufs(bt.cs->d);
-  const int n = p.n, K = p.k;
-  const size_t nn = (size_t)n * n;
-  const int per = (n * n + kThreads - 1) / kThreads;
-  const int b = blockIdx.x / per, pix = (blockIdx.x % per) * kThreads + threadIdx.x;
-  if (b >= bt.ns || pix >= n * n) return;
-  const int2 rc = d.pos[bt.slots[b]];
-  const int y = pix / n, x = pix - y * n;
-  const float2 o = d.obj[(size_t)(rc.x + y) * p.w_obj + rc.y + x];
-  // mode k + 1's probe value is loaded before mode k's store (a load behind a store
-  // would wait for it)
-  float2 pv = d.probe[pix];
-  for (int k = 0; k < K; ++k) {
-    const float2 pn = k + 1 < K ? d.probe[(size_t)(k + 1) * nn + pix] : pv;
-    d.X[((size_t)b * K + k) * nn + pix] = cmul(o, pv);
-    pv = pn;
-  }
 }
 
 // Side work of the batch (see side_job) as its own launch.
@@ -485,21 +490,39 @@ bool dft_supported(int n) { return n == 64 || n == 128 || n == 192 || n == 256; 
 int dft_err_slots(int n) { return (n / kDftTile) * (n / kDftTile); }
 
 template <int N>
-static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inverse, hipStream_t s) {
+static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inverse, hipStream_t s,
+                         const CaseDesc* exit_cases = nullptr, int beta = 0, const int* it = nullptr) {
   static_assert(N % (16 * kDftGroups) == 0, "whole row / column groups per block");
   constexpr int W = (N % 128 == 0) ? 8 : 4;  // two waves per SIMD where the tiles divide
   DftPlanes F{planes};
   const int rows = frames * N;
+  const dim3 rgrid(rows / (16 * kDftGroups)), lgrid(N / (16 * kDftGroups), frames);
   if (!inverse) {
-    pty_launch(k_dft_right<N, false, W>, dim3(rows / (16 * kDftGroups)), dim3(64 * W), 0, s, X, F, rows);
-    pty_launch(k_dft_left<N, false, W>, dim3(N / (16 * kDftGroups), frames), dim3(64 * W), 0, s, X, F, frames);
+    if (exit_cases)
+      pty_launch(k_dft_right<N, false, W, true>, rgrid, dim3(64 * W), 0, s, X, F, rows, exit_cases, beta, it);
+    else
+      pty_launch(k_dft_right<N, false, W, false>, rgrid, dim3(64 * W), 0, s, X, F, rows, (const CaseDesc*)nullptr,
+                 0, (const int*)nullptr);
+    pty_launch(k_dft_left<N, false, W>, lgrid, dim3(64 * W), 0, s, X, F, frames);
   } else {
-    pty_launch(k_dft_left<N, true, W>, dim3(N / (16 * kDftGroups), frames), dim3(64 * W), 0, s, X, F, frames);
-    pty_launch(k_dft_right<N, true, W>, dim3(rows / (16 * kDftGroups)), dim3(64 * W), 0, s, X, F, rows);
+    pty_launch(k_dft_left<N, true, W>, lgrid, dim3(64 * W), 0, s, X, F, frames);
+    pty_launch(k_dft_right<N, true, W, false>, rgrid, dim3(64 * W), 0, s, X, F, rows, (const CaseDesc*)nullptr, 0,
+               (const int*)nullptr);
   }
   return hipGetLastError();
 }
 
+hipError_t launch_dft2_exit(float2* X, const void* planes, const CaseDesc* cases, int beta, const int* it, int n,
+                           int frames, hipStream_t s) {
+  const __bf16* pl = static_cast<const __bf16*>(planes);
+  switch (n) {
+    case 64: return dft2_t<64>(X, pl, frames, false, s, cases, beta, it);
+    case 128: return dft2_t<128>(X, pl, frames, false, s, cases, beta, it);
+    case 192: return dft2_t<192>(X, pl, frames, false, s, cases, beta, it);
+    case 256: return dft2_t<256>(X, pl, frames, false, s, cases, beta, it);
+    default: return hipErrorInvalidValue;
+  }
+}
 hipError_t launch_dft2(float2* X, const void* planes, int n, int frames, bool inverse, hipStream_t s) {
   const __bf16* pl = static_cast<const __bf16*>(planes);
   switch (n) {
@@ -515,11 +538,6 @@ static int pix_blocks(int n) { return (n * n + kThreads - 1) / kThreads; }
 
 hipError_t launch_dft_side(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
   pty_launch(k_dft_side, dim3(t.max_side_jobs, t.n_cases), dim3(kThreads), 0, s, cases, beta, it);
-  return hipGetLastError();
-}
-hipError_t launch_dft_exit(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {
-  pty_launch(k_dft_exit, dim3(pix_blocks(t.n) * t.max_batch, t.n_cases), dim3(kThreads), 0, s, cases, beta,
-                     it);
   return hipGetLastError();
 }
 hipError_t launch_dft_modsum(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s) {

@@ -238,8 +238,11 @@ hipError_t launch_mono_cgls(const float* b, float* x, const MonoWork& w, int n, 
 bool dft_supported(int n);
 int dft_err_slots(int n);
 hipError_t launch_dft2(float2* X, const void* planes, int n, int frames, bool inverse, hipStream_t s);
+// The forward transform of batch beta's exit waves (frame b K + k = o_b P_k, formed
+// while the first GEMM stages its operand) into X.
+hipError_t launch_dft2_exit(float2* X, const void* planes, const CaseDesc* cases, int beta, const int* it, int n,
+                           int frames, hipStream_t s);
 hipError_t launch_dft_side(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
-hipError_t launch_dft_exit(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_dft_modsum(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_dft_blur_apply(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);
 hipError_t launch_dft_delta(const CaseDesc* cases, const TableShape& t, int beta, const int* it, hipStream_t s);

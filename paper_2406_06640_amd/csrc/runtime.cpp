@@ -498,8 +498,7 @@ std::string launch_batch_dft(ptycho_ctx* tc, const ptycho_ctx* c, const CaseDesc
                              const TableShape& sh, int beta, int ns, const int* it, hipStream_t s) {
   const int frames = ns * c->prm.n_modes;
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_side(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_exit(cases, sh, beta, it, s));
-  LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, false, s));
+  LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2_exit(X, c->d_planes, cases, beta, it, sh.n, frames, s));
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_modsum(cases, sh, beta, it, s));
   LAUNCH(tc, KC_DFT_OTHER, s, launch_dft_blur_apply(cases, sh, beta, it, s));
   LAUNCH(tc, KC_DFT_GEMM, s, launch_dft2(X, c->d_planes, sh.n, frames, true, s));
