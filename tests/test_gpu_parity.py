@@ -76,6 +76,11 @@ STEP_CASES = {
                      dict(batch=2, probe_update_start=5), [1, 2], 3),
     "far_n128_k4": (dict(n=128, k=4, obj=(200, 200), n_side=3, step=24, radius=30),
                     dict(batch=3), [0, 4, 8], 1),
+    # odd batches at sizes with the paired inverse row pass: the last pair has one slot
+    "far_n256_k2_odd_pairs": (dict(n=256, k=2, obj=(320, 320), n_side=3, step=24, radius=48),
+                              dict(batch=5, sigma1=2.0, sigma2=2.0), [8, 0, 4, 2, 6], 1),
+    "near_n512_k2_odd_pairs": (dict(n=512, k=2, geometry=1, obj=(576, 576), n_side=2, step=48, radius=100),
+                               dict(batch=3, sigma1=1.5, sigma2=1.5), [3, 0, 1], 1),
 }
 
 
