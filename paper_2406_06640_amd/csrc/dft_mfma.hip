@@ -104,12 +104,12 @@ __device__ __forceinline__ void cmma_bn(const CFrag& a, const CFrag& b, bf16x8 n
 // each), else 4.
 constexpr int kDftGroups = 4;
 
-// LDS stage of one chunk: [group][plane rh, rl, ih, il, then the negated pair the
-// complex product needs: -ih, -il or -rh, -rl][lane] fragments.
+// LDS stage of one chunk: [group][plane rh, rl, ih, il][lane] fragments.  The negated
+// pair the complex product needs (-ih, -il or -rh, -rl) is formed in registers once
+// per group and chunk by every reading wave.
 struct DftStage {
-  bf16x8 f[kDftGroups][6][64];
+  bf16x8 f[kDftGroups][4][64];
 };
-template <bool NEG_RE>
 __device__ __forceinline__ void dft_stage_put(DftStage& st, int g, int lane, const float2* v) {
   float re[8], im[8];
 #pragma unroll
@@ -124,8 +124,6 @@ __device__ __forceinline__ void dft_stage_put(DftStage& st, int g, int lane, con
   st.f[g][1][lane] = rl;
   st.f[g][2][lane] = ih;
   st.f[g][3][lane] = il;
-  st.f[g][4][lane] = NEG_RE ? neg8(rh) : neg8(ih);
-  st.f[g][5][lane] = NEG_RE ? neg8(rl) : neg8(il);
 }
 __device__ __forceinline__ CFrag dft_stage_get(const DftStage& st, int g, int lane) {
   return CFrag{st.f[g][0][lane], st.f[g][1][lane], st.f[g][2][lane], st.f[g][3][lane]};
@@ -208,7 +206,7 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
   float2 nx[8];
   if (stager) {
     load_chunk(0, nx);
-    dft_stage_put<INV>(stage[0], w, lane, nx);
+    dft_stage_put(stage[0], w, lane, nx);
   }
   __syncthreads();
   for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
@@ -220,8 +218,8 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       a[g] = dft_stage_get(stage[cur], g, lane);
-      na_h[g] = stage[cur].f[g][4][lane];
-      na_l[g] = stage[cur].f[g][5][lane];
+      na_h[g] = neg8(INV ? a[g].rh : a[g].ih);
+      na_l[g] = neg8(INV ? a[g].rl : a[g].il);
     }
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
@@ -233,7 +231,7 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
       b = b1;
       b1 = b2;
     }
-    if (more && stager) dft_stage_put<INV>(stage[cur ^ 1], w, lane, nx);
+    if (more && stager) dft_stage_put(stage[cur ^ 1], w, lane, nx);
     // the next chunk is staged, and (after the last chunk) every wave has read the
     // block's rows before any is overwritten
     __syncthreads();
@@ -295,7 +293,7 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
   if (stager) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) nx[i] = xcol[(size_t)i * N];
-    dft_stage_put<INV>(stage[0], w, lane, nx);
+    dft_stage_put(stage[0], w, lane, nx);
   }
   __syncthreads();
   for (int kc = 0, it = 0; kc < N; kc += 32, ++it) {
@@ -310,8 +308,8 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       b[g] = dft_stage_get(stage[cur], g, lane);
-      nb_h[g] = stage[cur].f[g][4][lane];
-      nb_l[g] = stage[cur].f[g][5][lane];
+      nb_h[g] = neg8(INV ? b[g].rh : b[g].ih);
+      nb_l[g] = neg8(INV ? b[g].rl : b[g].il);
     }
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
@@ -323,7 +321,7 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
       a = a1;
       a1 = a2;
     }
-    if (more && stager) dft_stage_put<INV>(stage[cur ^ 1], w, lane, nx);
+    if (more && stager) dft_stage_put(stage[cur ^ 1], w, lane, nx);
     __syncthreads();
   }
 #pragma unroll
