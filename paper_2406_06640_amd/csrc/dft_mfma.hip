@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
     return CFrag{F.frag(0, N, rt, kb, lane), F.frag(1, N, rt, kb, lane), F.frag(2, N, rt, kb, lane),
                  F.frag(3, N, rt, kb, lane)};
   };
-  const bool stager = w < G;  // waves 0..G-1 stage one row group each
+  const bool stager = W == G || w < G;  // waves 0..G-1 stage one row group each
   // table fragments run two tiles ahead: b (this tile), b1 (the next), loads for the one after
   auto tile_at = [&](int kb, int t, CFrag& dst) {
     while (t >= TPW) {  // TPW may be 1: two tiles ahead can be two chunks ahead
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
   };
   CFrag a = load_a(0, 0), a1 = a;
   tile_at(0, 1, a1);
-  const bool stager = w < G;  // waves 0..G-1 stage one column group each
+  const bool stager = W == G || w < G;  // waves 0..G-1 stage one column group each
   const float2* xcol = fr + (size_t)(kq * 8) * N + c0 + (stager ? w : 0) * 16 + lc;
   float2 nx[8];
   if (stager) {
