@@ -630,8 +630,9 @@ __global__ __launch_bounds__(1024) void k_fm_object(uint64_t key, long first, in
 // sample), 256 threads as 16 x 16, each owning outputs (ty + 16 a, tx + 16 b)):
 // for each of n_wl wavelength scales s, psi = exp(s (lnA + i phi)) P and
 // Psi = F_s psi F_s^T with F_s[u][x] = exp(-2 pi i s (u - 32)(x - 32) / 64) / 8
-// (two dense complex products staged in LDS); the mean |Psi|^2 is blurred by
-// the normalised periodic full-frame Gaussian (separable), written with its total.
+// (two dense complex products of the LDS-staged operands on FP32 matrix cores);
+// the mean |Psi|^2 is blurred by the normalised periodic full-frame Gaussian
+// (separable), written with its total.
 __global__ __launch_bounds__(256) void k_fm_patterns(const float2* __restrict__ obj, int side,
                                                      const float* __restrict__ sp, const int* __restrict__ pos,
                                                      int n_pos, int n_wl, float* __restrict__ pat,
@@ -681,54 +682,68 @@ __global__ __launch_bounds__(256) void k_fm_patterns(const float2* __restrict__ 
       X[e] = v;
     }
     __syncthreads();
-    float2 acc[4][4];
+    // Y1 = X Ft, then Y2 = F Y1 (F = Ft^T), on v_mfma_f32_16x16x4_f32: wave w owns
+    // output rows 16 w .. 16 w + 15 of each product, four 16-column tiles; per step
+    // of 4 along k, lane l supplies A[row l % 16][k l / 16] and B[k l / 16][col l % 16]
+    // and holds C[row 4 (l / 16) + r][col l % 16], r < 4.  A complex product is four
+    // real ones (the imaginary part of A negated once per step for the real part).
+    floatx4 cr[4], ci[4];
+    auto cmac = [&](float2 av, const float2* bv) {
+      const float nai = -av.y;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int t = 0; t < 4; ++t) {
+        cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[t].x, cr[t], 0, 0, 0);
+        cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bv[t].y, cr[t], 0, 0, 0);
+        ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[t].y, ci[t], 0, 0, 0);
+        ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[t].x, ci[t], 0, 0, 0);
+      }
+    };
+    const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
-    for (int x = 0; x < N; ++x) {
-      float2 xa[4], fb[4];
+    for (int t = 0; t < 4; ++t) cr[t] = ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < N; k0 += 4) {
+      const float2 av = X[(16 * wv + lr) * N + k0 + lk];
+      float2 bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xa[a] = X[(ty + 16 * a) * N + x];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) fb[b] = Ft[x * N + tx + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[a][b].x += xa[a].x * fb[b].x - xa[a].y * fb[b].y;
-          acc[a][b].y += xa[a].x * fb[b].y + xa[a].y * fb[b].x;
-        }
+      for (int t = 0; t < 4; ++t) bv[t] = Ft[(k0 + lk) * N + 16 * t + lr];
+      cmac(av, bv);
     }
+    __syncthreads();  // every wave has read X before Y1 overwrites it
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[(16 * wv + 4 * lk + r) * N + 16 * t + lr] = make_float2(cr[t][r], ci[t][r]);
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int t = 0; t < 4; ++t) cr[t] = ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < N; k0 += 4) {
+      const float2 av = Ft[(k0 + lk) * N + 16 * wv + lr];  // F[row][k] = Ft[k][row]
+      float2 bv[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) X[(ty + 16 * a) * N + tx + 16 * b] = acc[a][b];
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
-    for (int y = 0; y < N; ++y) {
-      float2 fa[4], xb[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) fa[a] = Ft[y * N + ty + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) xb[b] = X[y * N + tx + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[a][b].x += fa[a].x * xb[b].x - fa[a].y * xb[b].y;
-          acc[a][b].y += fa[a].x * xb[b].y + fa[a].y * xb[b].x;
-        }
+      for (int t = 0; t < 4; ++t) bv[t] = X[(k0 + lk) * N + 16 * t + lr];
+      cmac(av, bv);
     }
     const float wgt = 1.f / (float)n_wl;
 #pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) I[t * 4 + r] += wgt * (cr[t][r] * cr[t][r] + ci[t][r] * ci[t][r]);
+  }
+  // I[t * 4 + r] is output (16 wv + 4 lk + r, 16 t + lr); move it to the (ty + 16 a,
+  // tx + 16 b) ownership of the blur and the store below
+  {
+    float* ib = reinterpret_cast<float*>(X);
+    const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ib[(16 * wv + 4 * lk + r) * N + 16 * t + lr] = I[t * 4 + r];
+    __syncthreads();
+#pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) I[a * 4 + b] += wgt * (acc[a][b].x * acc[a][b].x + acc[a][b].y * acc[a][b].y);
+      for (int b = 0; b < 4; ++b) I[a * 4 + b] = ib[(ty + 16 * a) * N + tx + 16 * b];
   }
   if (sigma > 0.f) {
     float* ib = reinterpret_cast<float*>(X);
