@@ -701,6 +701,7 @@ __global__ __launch_bounds__(256) void k_fm_patterns(const float2* __restrict__ 
     const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
 #pragma unroll
     for (int t = 0; t < 4; ++t) cr[t] = ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int k0 = 0; k0 < N; k0 += 4) {
       const float2 av = X[(16 * wv + lr) * N + k0 + lk];
       float2 bv[4];
@@ -716,6 +717,7 @@ __global__ __launch_bounds__(256) void k_fm_patterns(const float2* __restrict__ 
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 4; ++t) cr[t] = ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int k0 = 0; k0 < N; k0 += 4) {
       const float2 av = Ft[(k0 + lk) * N + 16 * wv + lr];  // F[row][k] = Ft[k][row]
       float2 bv[4];
@@ -766,6 +768,7 @@ __global__ __launch_bounds__(256) void k_fm_patterns(const float2* __restrict__ 
       for (int b = 0; b < 4; ++b) {
         const int v = ty + 16 * a, u = tx + 16 * b;
         float s = 0.f;
+#pragma unroll 4
         for (int d = 0; d < N; ++d) s += g[d] * ib[v * N + ((u - d) & (N - 1))];
         tmp[a * 4 + b] = s;
       }
@@ -781,6 +784,7 @@ __global__ __launch_bounds__(256) void k_fm_patterns(const float2* __restrict__ 
       for (int b = 0; b < 4; ++b) {
         const int v = ty + 16 * a, u = tx + 16 * b;
         float s = 0.f;
+#pragma unroll 4
         for (int d = 0; d < N; ++d) s += g[d] * ib[((v - d) & (N - 1)) * N + u];
         I[a * 4 + b] = s / (gs * gs);
       }
