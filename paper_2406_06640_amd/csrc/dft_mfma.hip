@@ -226,8 +226,12 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
       // the table fragment two tiles ahead loads during this tile's MFMAs
       CFrag b2 = b1;
       tile_at(kc / 32, t + 2, b2);
+      // with one wave per SIMD the MFMA stream takes issue priority over the other
+      // workgroups' loads (measured +2-4 % at N = 192; with two waves per SIMD, slower)
+      if constexpr (W == G) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int g = 0; g < G; ++g) cmma_n(a[g], na_h[g], na_l[g], b, INV, cr[g][t], ci[g][t]);
+      if constexpr (W == G) __builtin_amdgcn_s_setprio(0);
       b = b1;
       b1 = b2;
     }
@@ -316,8 +320,10 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
       // the table fragment two tiles ahead loads during this tile's MFMAs
       CFrag a2 = a1;
       tile_at(kc / 32, t + 2, a2);
+      if constexpr (W == G) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int g = 0; g < G; ++g) cmma_bn(a, b[g], nb_h[g], nb_l[g], INV, cr[g][t], ci[g][t]);
+      if constexpr (W == G) __builtin_amdgcn_s_setprio(0);
       a = a1;
       a1 = a2;
     }
