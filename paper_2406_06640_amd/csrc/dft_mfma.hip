@@ -101,7 +101,7 @@ __device__ __forceinline__ void cmma_bn(const CFrag& a, const CFrag& b, bf16x8 n
 // (double-buffered), loading the next chunk's slice while the current chunk's MFMAs
 // run; the table fragments run two tiles ahead of the MFMAs.  W = 8 where N/16 splits
 // into 8 equal shares of output tiles (two waves per SIMD, 64 accumulator registers
-// each), else 4.
+// each), 12 at N = 192 (one tile per wave), else 4.
 constexpr int kDftGroups = 4;
 
 // LDS stage of one chunk: [group][plane rh, rl, ih, il][lane] fragments.  The negated
@@ -226,12 +226,8 @@ __global__ __launch_bounds__(64 * W) void k_dft_right(float2* __restrict__ X, Df
       // the table fragment two tiles ahead loads during this tile's MFMAs
       CFrag b2 = b1;
       tile_at(kc / 32, t + 2, b2);
-      // with one wave per SIMD the MFMA stream takes issue priority over the other
-      // workgroups' loads (measured +2-4 % at N = 192; with two waves per SIMD, slower)
-      if constexpr (W == G) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int g = 0; g < G; ++g) cmma_n(a[g], na_h[g], na_l[g], b, INV, cr[g][t], ci[g][t]);
-      if constexpr (W == G) __builtin_amdgcn_s_setprio(0);
       b = b1;
       b1 = b2;
     }
@@ -320,10 +316,8 @@ __global__ __launch_bounds__(64 * W) void k_dft_left(float2* __restrict__ X, Dft
       // the table fragment two tiles ahead loads during this tile's MFMAs
       CFrag a2 = a1;
       tile_at(kc / 32, t + 2, a2);
-      if constexpr (W == G) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int g = 0; g < G; ++g) cmma_bn(a, b[g], nb_h[g], nb_l[g], INV, cr[g][t], ci[g][t]);
-      if constexpr (W == G) __builtin_amdgcn_s_setprio(0);
       a = a1;
       a1 = a2;
     }
@@ -497,7 +491,9 @@ template <int N>
 static hipError_t dft2_t(float2* X, const __bf16* planes, int frames, bool inverse, hipStream_t s,
                          const CaseDesc* exit_cases = nullptr, int beta = 0, const int* it = nullptr) {
   static_assert(N % (16 * kDftGroups) == 0, "whole row / column groups per block");
-  constexpr int W = (N % 128 == 0) ? 8 : 4;  // two waves per SIMD where the tiles divide
+  // two waves per SIMD where the tiles divide into eight shares, three at N = 192 (twelve
+  // waves of one 16-column tile each)
+  constexpr int W = N == 192 ? 12 : (N % 128 == 0) ? 8 : 4;
   DftPlanes F{planes};
   const int rows = frames * N;
   const dim3 rgrid(rows / (16 * kDftGroups)), lgrid(N / (16 * kDftGroups), frames);
